@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Benchmark: time-to-1e-10 of FP16-IR GADI vs plain FP64 GADI on one MI355X.
+
+One step = one complete GADI-IR solve (every hot-path phase: FP64 residual,
+CG on alpha I + H, CGNE on alpha I + S, FP64 update, repeated to RES <= 1e-10)
+of the 3-D convection-diffusion system, 128^3 grid, beta = (20, 20, 20),
+b = A x* with x* ~ U(-1, 1) seed 0, inputs resident in device memory.
+
+Prints one JSON line.  The plain FP64 GADI solve (inner CG/CGNE to 1e-6) is
+timed on the same GPU for the comparison; the FP64 CPU oracle is timed on a
+bounded sample of outer sweeps on the host cores (cpu_baseline leg).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1e-10 residual & SpMV HBM GB/s: FP16-IR+MLP vs plain FP64 GADI"
+HBM_PEAK_GBS = 8000.0
+WEIGHTS = os.path.join(ROOT, "paper_2501_04229_amd", "predictor", "mlp_weights.npz")
+
+
+def solve_bytes(prec: str, n: int, z: int, zs: int, sweeps: int, inner_h: int, inner_s: int) -> float:
+    """Algorithmic HBM bytes of one solve launch.
+
+    Per unit (value + int32 index per stored entry, each vector read or written once):
+      residual a1          12 z + 22 N   (A in double, x/b in double, scaled half output)
+      update a6            6 z_S + 26 N  (one S product on the half CGNE solution + x read/write)
+      CG step on alpha I+H     6 z + 16 N   (half values)      | 12 z + 32 N (double)
+      CGNE step on alpha I+S   12 z_S + 16 N (two S products)  | 24 z_S + 32 N (double)
+    One residual more than corrections is evaluated (the converged one)."""
+    if prec == "fp64":
+        cg, cgne, upd = 12 * z + 32 * n, 24 * zs + 32 * n, 12 * zs + 32 * n
+    elif prec == "fp32":
+        cg, cgne, upd = 8 * z + 24 * n, 16 * zs + 24 * n, 8 * zs + 30 * n
+    else:
+        cg, cgne, upd = 6 * z + 16 * n, 12 * zs + 16 * n, 6 * zs + 26 * n
+    res = 12 * z + 22 * n
+    return float((sweeps + 1) * res + sweeps * upd + inner_h * cg + inner_s * cgne)
+
+
+def choose_params(g, A, use_mlp: bool):
+    """(alpha, omega) from the trained predictor if its weights exist, else the default (0.5, 0.5)."""
+    if use_mlp and os.path.exists(WEIGHTS):
+        import paper_2501_04229_amd as gadi
+        d = np.load(WEIGHTS)
+        p = gadi.Predictor()
+        p.set_weights(d["weights"])
+        p.set_norm(d["mu"], d["sd"])
+        f = g.features(A.dim, A.grid, A.beta)
+        a, w = p.predict(f)
+        return a, w, "mlp"
+    return 0.5, 0.5, "default"
+
+
+def cpu_baseline(A, b, alpha, omega, sweeps_needed, eps, budget_s=20.0):
+    """FP64 oracle (plain GADI, the same algorithm) on the host: time a bounded
+    number of outer sweeps and scale per sweep to the sweeps the solve needs."""
+    import oracle
+    o = oracle.OracleSystem(A)
+    k = 1
+    t0 = time.perf_counter()
+    r = o.gadi(b, alpha, omega, tol=0.0, eps_h=eps, eps_s=eps, maxit_out=k)
+    t1 = time.perf_counter()
+    per = (t1 - t0) / k
+    k2 = max(1, min(int(budget_s / max(per, 1e-6)), 50))
+    t0 = time.perf_counter()
+    r = o.gadi(b, alpha, omega, tol=0.0, eps_h=eps, eps_s=eps, maxit_out=k2)
+    t1 = time.perf_counter()
+    per = (t1 - t0) / k2
+    return {
+        "value": per * sweeps_needed,
+        "unit": "s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{k2} FP64 GADI sweeps (inner CG/CGNE to {eps:g}) of the same system timed, "
+                  f"{per:.3f} s/sweep, scaled to the {sweeps_needed} sweeps plain FP64 GADI needs",
+        "seconds_per_sweep": per,
+        "sample_sweeps": k2,
+        "inner_h_per_sweep": r["inner_h"] / max(1, r["sweeps"]),
+    }
+
+
+def spmv_gbs(g, A, alpha, reps=50):
+    """Stand-alone fp16 (alpha I + H) product: algorithmic 6 z + 8 N bytes per launch."""
+    import torch
+    n = A.n
+    x = torch.rand(n, device="cuda", dtype=torch.float16)
+    y = torch.empty_like(x)
+    for _ in range(5):
+        g.spmv("H16", x, y, alpha)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.spmv("H16", x, y, alpha)
+    e1.record()
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) * 1e-3 / reps
+    by = 6.0 * A.nnz + 8.0 * n
+    y64 = torch.empty(n, device="cuda", dtype=torch.float64)
+    x64 = torch.rand(n, device="cuda", dtype=torch.float64)
+    for _ in range(5):
+        g.spmv("A", x64, y64)
+    e0.record()
+    for _ in range(reps):
+        g.spmv("A", x64, y64)
+    e1.record()
+    torch.cuda.synchronize()
+    dt64 = e0.elapsed_time(e1) * 1e-3 / reps
+    by64 = 12.0 * A.nnz + 20.0 * n
+    return {"fp16_H_us": dt * 1e6, "fp16_H_GBs": by / dt / 1e9, "fp64_A_us": dt64 * 1e6,
+            "fp64_A_GBs": by64 / dt64 / 1e9}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="convdiff3d_128_beta20")
+    ap.add_argument("--prec", default="fp16", choices=["fp16", "fp32", "fp64"])
+    ap.add_argument("--eps-inner", type=float, default=None)
+    ap.add_argument("--params", default="mlp", choices=["mlp", "default"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver is a single-GPU build.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import gadi_inputs as gi
+    import paper_2501_04229_amd as gadi
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    t_setup = time.perf_counter()
+    W = gi.workload(args.workload)
+    A, b, xs = W["A"], W["b"], W["xstar"]
+    g = gadi.System(A)
+    setup_s = time.perf_counter() - t_setup
+    z = A.nnz
+    zs = A.nnz - A.n
+    n = A.n
+    bd = torch.from_numpy(b).cuda()
+    alpha, omega, psrc = choose_params(g, A, args.params == "mlp")
+    eps = args.eps_inner
+
+    def run(prec, al, om, e):
+        x, info = g.solve(bd, al, om, tol=1e-10, prec=prec, eps_inner=e)
+        return x, info
+
+    print(f"# workload {args.workload}: N={n} nnz={z} setup {setup_s:.1f}s params {psrc} "
+          f"alpha={alpha:.4g} omega={omega:.4g}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        x, info = run(args.prec, alpha, omega, eps)
+        print(f"# warmup: {info['status_str']} sweeps={info['outer_sweeps']} inner_H={info['inner_H']} "
+              f"inner_S={info['inner_S']} {info['seconds']:.3f}s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kernel_s = []
+    infos = []
+    for _ in range(args.steps):
+        x, info = run(args.prec, alpha, omega, eps)
+        kernel_s.append(info["seconds"])
+        infos.append(info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    step_s = (t1 - t0) / args.steps
+    info = infos[-1]
+    if info["status"] != gadi.OK:
+        print(f"# solve did not converge: {info}", file=sys.stderr, flush=True)
+    xh = x.cpu().numpy()
+    rel_err_xstar = float(np.linalg.norm(xh - xs) / np.linalg.norm(xs))
+    kern = float(np.mean(kernel_s))
+    nbytes = solve_bytes(args.prec, n, z, zs, info["outer_sweeps"], info["inner_H"], info["inner_S"])
+    achieved = nbytes / kern / 1e9
+    print(f"# fp16-IR: {step_s:.3f}s/solve, kernel {kern:.3f}s, {achieved:.0f} GB/s algorithmic, "
+          f"sweeps={info['outer_sweeps']} inner_H={info['inner_H']} inner_S={info['inner_S']} "
+          f"relres={info['relres']:.3e} err_vs_x*={rel_err_xstar:.3e} barriers={info['barriers']} "
+          f"block0 in barriers {info['barrier_seconds']:.3f}s", file=sys.stderr, flush=True)
+
+    fp64 = None
+    if not args.no_fp64:
+        x64, i64 = run("fp64", 0.5, 0.5, 1e-6)
+        torch.cuda.synchronize()
+        x64h = x64.cpu().numpy()
+        nb64 = solve_bytes("fp64", n, z, zs, i64["outer_sweeps"], i64["inner_H"], i64["inner_S"])
+        fp64 = {"seconds": i64["seconds"], "status": i64["status_str"], "sweeps": i64["outer_sweeps"],
+                "inner_H": i64["inner_H"], "inner_S": i64["inner_S"], "relres": i64["relres"],
+                "rel_err_vs_xstar": float(np.linalg.norm(x64h - xs) / np.linalg.norm(xs)),
+                "algorithmic_GBs": nb64 / i64["seconds"] / 1e9,
+                "rel_diff_vs_fp16ir": float(np.linalg.norm(xh - x64h) / np.linalg.norm(x64h))}
+        print(f"# fp64 GADI: {i64['seconds']:.3f}s sweeps={i64['outer_sweeps']} inner_H={i64['inner_H']} "
+              f"inner_S={i64['inner_S']} relres={i64['relres']:.3e}", file=sys.stderr, flush=True)
+    sp = spmv_gbs(g, A, alpha)
+    print(f"# spmv: {sp}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu:
+        sweeps_needed = fp64["sweeps"] if fp64 else info["outer_sweeps"]
+        cpu = cpu_baseline(A, b, 0.5, 0.5, sweeps_needed, 1e-6)
+        print(f"# cpu oracle: {cpu['seconds_per_sweep']:.3f}s/sweep on {cpu['cores']} threads -> "
+              f"{cpu['value']:.1f}s", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": step_s,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": {"fp16": "fp16 storage / fp32 arithmetic inner, f64 residual+update",
+                  "fp32": "f32 inner, f64 residual+update", "fp64": "f64"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "N": n, "nnz": z, "tol": 1e-10,
+                   "eps_inner": eps if eps is not None else (1e-6 if args.prec == "fp64" else 1e-3),
+                   "alpha": alpha, "omega": omega, "params": psrc, "prec": args.prec,
+                   "solve_kernel_blocks": g.solver_blocks()},
+        "solve": {"status": info["status_str"], "sweeps": info["outer_sweeps"], "inner_H": info["inner_H"],
+                  "inner_S": info["inner_S"], "relres": info["relres"], "rel_err_vs_xstar": rel_err_xstar,
+                  "kernel_seconds": kern, "barriers": info["barriers"],
+                  "barrier_seconds_block0": info["barrier_seconds"]},
+        "fp64_gadi": fp64,
+        "speedup_vs_fp64_gadi": (fp64["seconds"] / kern) if fp64 else None,
+        "spmv": sp,
+        "roofline": {"bound": "hbm", "kernel": f"solve_kernel<{args.prec}>", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "algorithmic_bytes_per_launch": nbytes, "launch_seconds": kern, "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

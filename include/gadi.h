@@ -1,0 +1,198 @@
+/*
+ * gadi.h -- C ABI of libgadi.so, a GADI-IR sparse solver for AMD MI355X (gfx950).
+ *
+ * Method: three-precision iterative refinement around the general
+ * alternating-direction implicit (GADI) iteration (Algorithm 1, Section 2.1 of
+ * Ge and Zhang, "Three-precision iterative refinement with parameter
+ * regularization and prediction for solving large sparse linear systems").
+ * With the Hermitian/skew-Hermitian splitting A = H + S of Section 4.1,
+ * H = (A + A^T)/2, S = (A - A^T)/2, one outer sweep is
+ *   1. r = b - A x                               (residual, u_f = double)
+ *   2. (alpha I + H) z = r                       (CG,   u_r = inner precision)
+ *   3. (alpha I + S) y = (2 - omega) alpha z     (CGNE, u_r = inner precision)
+ *   4. x = x + y                                 (update, u = double)
+ * repeated until ||r||_2 <= tol ||r_0||_2 (the RES of Section 4.1).
+ *
+ * Conventions for every entry point:
+ *   - Nothing aborts or throws across the ABI; each call returns a gadi_status.
+ *   - Pointers flagged "device" are HIP device pointers on the current device;
+ *     "host" pointers are ordinary host memory.  Vectors are contiguous,
+ *     unit-stride, length n.
+ *   - Work is enqueued on the stream bound with gadi_set_stream (default: the
+ *     null stream).  Calls that return results to the host synchronise that
+ *     stream before returning.
+ *   - Handles are not thread-safe: calls on one handle must not overlap.
+ */
+#ifndef GADI_H
+#define GADI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GADI_OK = 0,
+  GADI_EINVAL = 1,      /* bad argument or malformed CSR */
+  GADI_ENOTSPD = 2,     /* an inner operator showed non-positive curvature */
+  GADI_EOVERFLOW16 = 3, /* a scaled half-precision quantity left the finite range */
+  GADI_EDIVERGED = 4,   /* non-finite residual or ||r|| > 1e6 ||r_0|| */
+  GADI_EMAXIT = 5,      /* outer sweep limit reached */
+  GADI_EHIP = 6,        /* a HIP runtime call failed */
+  GADI_ENOMEM = 7,      /* host or device allocation failed */
+  GADI_EBARRIER = 8     /* a device-wide barrier timed out (the kernel bailed out) */
+} gadi_status;
+
+/* Square CSR matrix, int32 indices, float64 values, read-only and owned by the
+ * caller; the library copies what it needs during gadi_setup.  Column indices
+ * within a row must be strictly increasing.  on_device != 0 means the three
+ * arrays are device pointers. */
+typedef struct {
+  int32_t n;
+  int64_t nnz;
+  const int32_t* row_ptr; /* [n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz */
+  const int32_t* col_idx; /* [nnz], 0 <= col < n */
+  const double* val;      /* [nnz] */
+  int32_t on_device;
+} gadi_csr;
+
+/* Splittings A = M + N.  Only the Hermitian/skew-Hermitian splitting of the
+ * paper's experiments (Section 4.1 equation) is provided. */
+typedef enum { GADI_SPLIT_HSS = 0 } gadi_splitting;
+
+/* Precision triple (u_r, u, u_f) of Algorithm 1. */
+typedef enum {
+  GADI_PREC_FP64 = 0,    /* u_r = u = u_f = double: plain GADI                  */
+  GADI_PREC_FP16_IR = 1, /* u_r = half (fp16 storage, fp32 arithmetic), u = u_f = double */
+  GADI_PREC_FP32_IR = 2  /* u_r = single, u = u_f = double                      */
+} gadi_precision;
+
+typedef struct {
+  gadi_precision prec;
+  double eps_inner;   /* inner stop: ||g - K z||_2 <= eps_inner ||g||_2 (recurrence residual) */
+  int32_t maxit_outer;  /* sweep limit (EMAXIT when reached)                   */
+  int32_t maxit_inner;  /* per inner solve                                      */
+  int32_t on_device;    /* 1: b and x are device pointers; 0: host pointers     */
+  int32_t record_history; /* 1: keep RES per sweep, read with gadi_get_history  */
+} gadi_options;
+
+typedef struct {
+  int32_t status;       /* gadi_status of the solve */
+  int32_t outer_sweeps; /* corrections applied */
+  int64_t inner_H;      /* total CG steps on alpha I + H */
+  int64_t inner_S;      /* total CGNE steps on alpha I + S */
+  double relres;        /* final ||r||_2 / ||r_0||_2 (FP64 residual with the true A) */
+  double seconds;       /* device time of the solve kernel */
+  double alpha, omega;  /* parameters used */
+  int32_t fell_back;    /* 1 if the caller's fallback rule replaced predicted parameters */
+  int64_t barriers;     /* device-wide barriers executed by the solve kernel */
+  double barrier_seconds; /* time block 0 spent inside device-wide barriers */
+} gadi_solve_info;
+
+typedef struct gadi_handle gadi_handle;
+typedef struct gadi_mlp gadi_mlp;
+
+/* Fill `o` with defaults: FP16_IR, eps_inner 1e-3 (fp16/fp32) , maxit_outer 20000,
+ * maxit_inner 2000, host pointers, no history. */
+void gadi_default_options(gadi_options* o, gadi_precision prec);
+
+/* Validate A, form H and S (Section 4.1 splitting) on the union pattern of A and
+ * A^T, pack A, H, S into the device layout and return a handle.  EINVAL on a
+ * malformed CSR or unsupported splitting; ENOMEM / EHIP on allocation failure.
+ * The handle owns all device memory it allocates. */
+gadi_status gadi_setup(const gadi_csr* A, gadi_splitting split, gadi_handle** out);
+
+/* Bind a hipStream_t (passed as void*) for all later work on the handle. */
+gadi_status gadi_set_stream(gadi_handle* h, void* stream);
+
+/* Run GADI-IR (Algorithm 1) from x_0 = x.  b: [n] float64, x: [n] float64 in/out
+ * (host or device per opts->on_device).  alpha > 0 and 0 <= omega < 2 (the
+ * convergence domain of Theorem 1), tol >= 0.  On return x holds the last
+ * iterate and info (may be NULL) is filled; the return value equals
+ * info->status.  EINVAL for bad parameters. */
+gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x, double alpha, double omega,
+                          double tol, const gadi_options* opts, gadi_solve_info* info);
+
+/* RES history of the last solve with record_history = 1: copies up to `cap`
+ * values (RES before each sweep) into `out` (host) and returns the count. */
+int32_t gadi_get_history(gadi_handle* h, double* out, int32_t cap);
+
+/* Many systems, many (alpha, omega) trials each, in one persistent launch.
+ * hs[nsys]: handles set up beforehand; b[s], x[s]: per-system host vectors
+ * (x[s] receives the last iterate of trial 0 of system s and may be NULL);
+ * alpha[t], omega[t] for t < ntrial (ntrial <= 16): the same trial grid for
+ * every system.  info[s * ntrial + t] receives each trial's record.  Trials
+ * start from x_0 = 0.  The parameter sweep of the paper's training-set
+ * generation (Section 3.3.2) uses this call. */
+gadi_status gadi_ir_solve_batched(gadi_handle* const* hs, int32_t nsys, const double* const* b,
+                                  double* const* x, const double* alpha, const double* omega,
+                                  int32_t ntrial, double tol, const gadi_options* opts,
+                                  gadi_solve_info* info);
+
+/* One product with the packed operators, for kernel-level checks and
+ * bandwidth measurement.  x, y are device pointers of length n.
+ *   which = 0: y = A x               float64 in/out
+ *   which = 1: y = (alpha I + H) x   fp16 in/out (half values), fp32 arithmetic
+ *   which = 2: y = (I + S / alpha) x fp16 in/out, fp32 arithmetic
+ *   which = 3: y = (alpha I + H) x   float64 in/out, float64 operator
+ * Enqueued on the bound stream; does not synchronise. */
+gadi_status gadi_spmv(gadi_handle* h, int32_t which, double alpha, const void* x, void* y);
+
+/* Copy the packed fp16 values of H (which = 1) or S (which = 2) back in CSR
+ * order of the union pattern: out_val[k] for the k-th stored entry of row i in
+ * ascending column order, including the diagonal.  out_rp [n+1], out_col and
+ * out_val [split nnz] are host arrays; pass NULL out_col/out_val to query the
+ * count through *nnz_out. */
+gadi_status gadi_get_split_fp16(gadi_handle* h, int32_t which, int32_t* out_rp, int32_t* out_col,
+                                uint16_t* out_val, int64_t* nnz_out);
+
+/* Predictor features (computed on the device from the packed splitting):
+ * out[8] = [ln n, dim, log10 mean(beta), max(beta) h/2 with h = 1/(grid+1),
+ *           min_i(H_ii - R_i^H), max_i(H_ii + R_i^H), max_i R_i^S, min_i R_i^S],
+ * R_i the off-diagonal absolute row sums.  dim, grid and beta[dim] describe the
+ * convection-diffusion problem (Section 4.1) and are caller-supplied. */
+gadi_status gadi_features(gadi_handle* h, int32_t dim, int32_t grid, const double* beta, float* out);
+
+/* ---- (alpha, omega) predictor: 8 -> 64 -> 64 -> 2 MLP, fp32, ReLU ----------
+ * Stands in for the parameter-prediction step of Section 3.3.  Targets are
+ * (log10 alpha, omega).  Weights are one flat fp32 vector of 4866 values in
+ * the order W1[64,8], b1[64], W2[64,64], b2[64], W3[2,64], b3[2]. */
+gadi_status gadi_mlp_create(uint64_t seed, gadi_mlp** out);
+gadi_status gadi_mlp_destroy(gadi_mlp* m);
+/* host weights in/out (4866 floats) */
+gadi_status gadi_mlp_set_weights(gadi_mlp* m, const float* w);
+gadi_status gadi_mlp_get_weights(gadi_mlp* m, float* w);
+/* feature standardisation: x_std = (x - mu) / sd, mu/sd [8] host */
+gadi_status gadi_mlp_set_norm(gadi_mlp* m, const float* mu, const float* sd);
+/* Forward pass on the device: X [B,8] host (raw features), Y [B,2] host out. */
+gadi_status gadi_mlp_forward(gadi_mlp* m, const float* X, int32_t B, float* Y);
+/* Loss (MSE over B*2 outputs) and gradient [4866] for standardised inputs
+ * Xs [B,8] and targets Y [B,2] (host), computed by the device kernels. */
+gadi_status gadi_mlp_loss_grad(gadi_mlp* m, const float* Xs, const float* Y, int32_t B, float* loss,
+                               float* grad);
+/* Train with Adam (beta1 0.9, beta2 0.999, eps 1e-8) for `epochs` full-batch
+ * steps on raw features X [n,8] and targets Y [n,2] (host); computes and stores
+ * the standardisation from X.  loss_out[epochs] (may be NULL) gets the loss
+ * before each step.  All arithmetic runs in the device kernels. */
+gadi_status gadi_train_mlp(gadi_mlp* m, const float* X, const float* Y, int32_t n, int32_t epochs,
+                           float lr, float* loss_out);
+/* Predict (alpha, omega) for one raw feature vector; alpha is clamped to
+ * [1e-3, 10] and omega to [0, 1.99]. */
+gadi_status gadi_predict_params(gadi_mlp* m, const float* features, double* alpha, double* omega);
+
+/* Release the handle and its device memory. */
+gadi_status gadi_destroy(gadi_handle* h);
+
+/* Static description of a status code. */
+const char* gadi_status_str(gadi_status s);
+
+/* Number of device blocks the persistent solve kernel uses for this handle
+ * (for measurement scripts); 0 on error. */
+int32_t gadi_solver_blocks(gadi_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GADI_H */

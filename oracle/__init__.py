@@ -83,6 +83,13 @@ def _declare(lib):
                                     ctypes.c_int, P(ctypes.c_int), i64p, i64p, f64p, f64p,
                                     ctypes.c_int]
         lib.oracle_gershgorin.argtypes = [ctypes.c_void_p, f64p]
+        lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_num_threads.argtypes = []
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(_lib().oracle_num_threads())
 
 
 def _ptr(a, ct):

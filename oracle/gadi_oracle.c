@@ -24,6 +24,9 @@
  * order, so results do not depend on the OpenMP thread count.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -390,4 +393,13 @@ int oracle_gershgorin(const oracle_sys* s, double* out) {
   out[2] = smax;
   out[3] = smin;
   return O_OK;
+}
+
+/* Threads the OpenMP loops of the oracle use (1 without OpenMP). */
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

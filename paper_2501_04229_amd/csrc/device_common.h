@@ -1,0 +1,302 @@
+// Device helpers shared by the solver kernels: precision modes, conversions,
+// the SELL-64 row product, and the device-wide barrier / all-reduce used by
+// the persistent launches.
+#pragma once
+
+#include "internal.h"
+
+namespace gadi {
+
+// Precision modes of the inner solves (u_r of Algorithm 1).  MT: stored value
+// type of H and S; VT: stored Krylov vectors; ST: inner solution accumulators;
+// RT: stored outer residual; AT: arithmetic.  The residual r = b - A x and the
+// update x += y always run in double (u_f = u = double).
+struct ModeF16 {
+  using MT = __half;
+  using VT = __half;
+  using ST = float;
+  using RT = float;
+  using AT = float;
+  static constexpr int id = GADI_PREC_FP16_IR;
+};
+struct ModeF32 {
+  using MT = float;
+  using VT = float;
+  using ST = float;
+  using RT = float;
+  using AT = float;
+  static constexpr int id = GADI_PREC_FP32_IR;
+};
+struct ModeF64 {
+  using MT = double;
+  using VT = double;
+  using ST = double;
+  using RT = double;
+  using AT = double;
+  static constexpr int id = GADI_PREC_FP64;
+};
+
+template <class AT>
+__device__ __forceinline__ AT ld(__half v) {
+  return (AT)__half2float(v);
+}
+template <class AT>
+__device__ __forceinline__ AT ld(float v) {
+  return (AT)v;
+}
+template <class AT>
+__device__ __forceinline__ AT ld(double v) {
+  return (AT)v;
+}
+
+template <class VT>
+struct Cvt;
+template <>
+struct Cvt<__half> {
+  template <class AT>
+  static __device__ __forceinline__ __half to(AT v) {
+    return __float2half_rn((float)v);
+  }
+};
+template <>
+struct Cvt<float> {
+  template <class AT>
+  static __device__ __forceinline__ float to(AT v) {
+    return (float)v;
+  }
+};
+template <>
+struct Cvt<double> {
+  template <class AT>
+  static __device__ __forceinline__ double to(AT v) {
+    return (double)v;
+  }
+};
+template <class VT, class AT>
+__device__ __forceinline__ VT st(AT v) {
+  return Cvt<VT>::template to<AT>(v);
+}
+
+// Off-diagonal part of one row of a SELL-64 operator: sum_j val_ij * fetch(col_ij)
+// over the row's slots in ascending column order.  W slots, unrolled so that
+// every index and value load is issued before the first gather.
+template <int W, class AT, class MT, class F>
+__device__ __forceinline__ AT row_sum_w(int k0, const int32_t* __restrict__ col, const MT* __restrict__ val,
+                                        F&& fetch) {
+  int c[W];
+  MT v[W];
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    c[j] = col[k0 + j * kSlice];
+    v[j] = val[k0 + j * kSlice];
+  }
+  AT acc = 0;
+#pragma unroll
+  for (int j = 0; j < W; ++j) acc += ld<AT>(v[j]) * fetch(c[j]);
+  return acc;
+}
+
+template <class AT, class MT, class F>
+__device__ __forceinline__ AT row_sum(int row, const int32_t* __restrict__ slice_ptr,
+                                      const int32_t* __restrict__ col, const MT* __restrict__ val, F&& fetch) {
+  // a wavefront covers exactly one slice, so the slice data are wave-uniform
+  const int s = __builtin_amdgcn_readfirstlane(row >> 6);
+  const int beg = slice_ptr[s];
+  const int w = (slice_ptr[s + 1] - beg) >> 6;
+  const int k0 = beg + (row & (kSlice - 1));
+  switch (w) {
+    case 0: return AT(0);
+    case 1: return row_sum_w<1, AT>(k0, col, val, fetch);
+    case 2: return row_sum_w<2, AT>(k0, col, val, fetch);
+    case 3: return row_sum_w<3, AT>(k0, col, val, fetch);
+    case 4: return row_sum_w<4, AT>(k0, col, val, fetch);
+    case 5: return row_sum_w<5, AT>(k0, col, val, fetch);
+    case 6: return row_sum_w<6, AT>(k0, col, val, fetch);
+    case 7: return row_sum_w<7, AT>(k0, col, val, fetch);
+    case 8: return row_sum_w<8, AT>(k0, col, val, fetch);
+    default: {
+      AT acc = 0;
+      for (int j = 0; j < w; ++j) {
+        const int k = k0 + j * kSlice;
+        acc += ld<AT>(val[k]) * fetch(col[k]);
+      }
+      return acc;
+    }
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Device-wide all-reduce + barrier for a persistent launch whose blocks are
+// all resident (cooperative launch).  Each block contributes three sums and
+// one maximum; every block receives the same four results.
+//
+// Arrival is contention free: a block publishes its partials, then its own
+// flag word (one 64-byte line per block).  Block 0 polls all flags with all
+// of its threads, combines the partials in block order (a fixed order, so the
+// result never depends on arrival order), publishes the result and releases
+// the grid through one word.  The agent-scope release before each flag store
+// and the acquire after each observed flag make the data written before the
+// barrier visible to every block after it.  A wait that exceeds `timeout`
+// wall-clock ticks sets the abort flag; the function then returns false in
+// every block and the caller must exit.
+struct Grid {
+  SyncState* sync;
+  unsigned long long* flags;
+  double* part;
+  double* result;
+  unsigned nblocks;
+  unsigned long long epoch;
+  long long timeout;
+  long long wait_ticks;  // block 0: wall-clock ticks spent inside barriers
+};
+
+struct Red4 {
+  double v[4];
+};
+
+template <int BLOCK>
+static __device__ __forceinline__ Red4 grid_allreduce(Grid& g, double s0, double s1, double s2, double m3,
+                                                      bool& ok) {
+  constexpr int NW = BLOCK / 64;
+  __shared__ double sh[NW][4];
+  __shared__ int sh_abort;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const long long t_enter = (blockIdx.x == 0 && tid == 0) ? wall_clock64() : 0;
+  {
+    const double a0 = wave_sum(s0), a1 = wave_sum(s1), a2 = wave_sum(s2), a3 = wave_max(m3);
+    if (lane == 0) {
+      sh[wid][0] = a0;
+      sh[wid][1] = a1;
+      sh[wid][2] = a2;
+      sh[wid][3] = a3;
+    }
+  }
+  __syncthreads();
+  g.epoch += 1;
+  const unsigned parity = (unsigned)(g.epoch & 1ull);
+  if (tid == 0) {
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      t0 += sh[w][0];
+      t1 += sh[w][1];
+      t2 += sh[w][2];
+      t3 = fmax(t3, sh[w][3]);
+    }
+    double* p = g.part + ((size_t)parity * kMaxBlocks + blockIdx.x) * 4;
+    p[0] = t0;
+    p[1] = t1;
+    p[2] = t2;
+    p[3] = t3;
+    sh_abort = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(g.flags + (size_t)blockIdx.x * kFlagStride, g.epoch, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (blockIdx.x == 0) {
+    // master: wait until every block has published this epoch
+    const long long t_start = wall_clock64();
+    for (;;) {
+      int mine = 1;
+      for (unsigned k = tid; k < g.nblocks; k += BLOCK)
+        if (__hip_atomic_load(g.flags + (size_t)k * kFlagStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+            g.epoch)
+          mine = 0;
+      if (__syncthreads_and(mine)) break;
+      const int expired = (tid == 0) && (wall_clock64() - t_start > g.timeout ||
+                                         __hip_atomic_load(&g.sync->abort, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT) != 0);
+      if (__syncthreads_or(expired)) {
+        if (tid == 0) {
+          __hip_atomic_store(&g.sync->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          sh_abort = 1;
+        }
+        break;
+      }
+    }
+    if (tid == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __syncthreads();
+    double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+    for (unsigned k = tid; k < g.nblocks; k += BLOCK) {
+      const double* p = g.part + ((size_t)parity * kMaxBlocks + k) * 4;
+      b0 += p[0];
+      b1 += p[1];
+      b2 += p[2];
+      b3 = fmax(b3, p[3]);
+    }
+    b0 = wave_sum(b0);
+    b1 = wave_sum(b1);
+    b2 = wave_sum(b2);
+    b3 = wave_max(b3);
+    __syncthreads();  // every wave has read sh[] above; reuse it
+    if (lane == 0) {
+      sh[wid][0] = b0;
+      sh[wid][1] = b1;
+      sh[wid][2] = b2;
+      sh[wid][3] = b3;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        r0 += sh[w][0];
+        r1 += sh[w][1];
+        r2 += sh[w][2];
+        r3 = fmax(r3, sh[w][3]);
+      }
+      double* r = g.result + parity * 4;
+      r[0] = r0;
+      r[1] = r1;
+      r[2] = r2;
+      r[3] = r3;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&g.sync->release, g.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if (tid == 0) {
+    const long long t_start = wall_clock64();
+    unsigned spins = 0;
+    while (__hip_atomic_load(&g.sync->release, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < g.epoch) {
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 255u) == 0u) {
+        if (__hip_atomic_load(&g.sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+            wall_clock64() - t_start > g.timeout) {
+          __hip_atomic_store(&g.sync->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          sh_abort = 1;
+          break;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  Red4 out;
+  const double* r = g.result + parity * 4;
+  out.v[0] = r[0];
+  out.v[1] = r[1];
+  out.v[2] = r[2];
+  out.v[3] = r[3];
+  ok = sh_abort == 0;
+  if (blockIdx.x == 0 && tid == 0) g.wait_ticks += wall_clock64() - t_enter;
+  __syncthreads();  // shared state is rewritten by the next call
+  return out;
+}
+
+// Logical block index: blocks are dealt to the 8 XCDs round-robin, so blocks
+// b, b+8, ... share an XCD and its L2.  The remap gives each XCD a contiguous
+// run of logical indices, hence a contiguous band of rows.
+__device__ __forceinline__ unsigned logical_block(unsigned b, unsigned G) {
+  return (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;
+}
+
+}  // namespace gadi

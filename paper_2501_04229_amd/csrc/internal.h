@@ -1,0 +1,112 @@
+// Internal types of libgadi: the device layout of one system and the solver
+// workspace.  Not part of the public ABI (include/gadi.h).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "gadi.h"
+
+namespace gadi {
+
+// Rows per SELL slice: one row per lane of a 64-wide wavefront.
+constexpr int kSlice = 64;
+// Threads (= rows) per block of the one-shot product kernels.
+constexpr int kRowBlock = 256;
+// Threads per block of the persistent solve kernels: 16 wavefronts, one block
+// per compute unit; a block step covers kTile = kSolveBlock rows (16 slices).
+constexpr int kSolveBlock = 1024;
+constexpr int kTile = kSolveBlock;
+// Row counts are padded to a whole number of solve tiles.
+constexpr int kPadRows = kTile;
+// Upper bound on blocks of any persistent launch (sizes the barrier buffers).
+constexpr int kMaxBlocks = 4096;
+// Stride between per-block arrival flags (one 64-byte line each).
+constexpr int kFlagStride = 8;
+
+#define GADI_HIP_CHECK(expr)                                \
+  do {                                                      \
+    hipError_t e_ = (expr);                                 \
+    if (e_ != hipSuccess) return fail_hip(e_, #expr, __FILE__, __LINE__); \
+  } while (0)
+
+gadi_status fail_hip(hipError_t e, const char* what, const char* file, int line);
+
+// Barrier / reduction state of a persistent launch (device memory).
+struct SyncState {
+  unsigned long long arrive;   // monotone arrival count
+  unsigned long long release;  // epoch released by the last arriving block
+  int abort;                   // set when a barrier wait timed out
+  int pad[5];
+};
+
+// Result record written by the solve kernel.
+struct DevInfo {
+  int status;
+  int sweeps;
+  long long inner_h;
+  long long inner_s;
+  double relres;
+  double rho0;
+  long long barriers;
+  long long barrier_ticks;
+};
+
+// One system in device layout.
+//   Off-diagonal entries of the union pattern of A and A^T are packed as
+//   SELL-64: slice s covers rows [64 s, 64 s + 64); its entries start at
+//   slice_ptr[s]; slot j of row (64 s + l) is element slice_ptr[s] + 64 j + l.
+//   The slice width is (slice_ptr[s+1] - slice_ptr[s]) / 64.  Padding slots
+//   hold col = row and value 0.  Diagonals are stored densely.
+struct System {
+  int n = 0;       // rows
+  int npad = 0;    // rows rounded up to a tile
+  int nslices = 0;
+  int64_t nnz_a = 0;      // stored entries of A
+  int64_t nnz_off = 0;    // off-diagonal entries of the union pattern
+  int64_t nslots = 0;     // SELL slots including padding
+  int max_width = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+
+  int32_t* slice_ptr = nullptr;  // [nslices + 1]
+  int32_t* col = nullptr;        // [nslots]
+  double* a_off = nullptr;       // [nslots] A values on the union pattern
+  double* a_diag = nullptr;      // [npad]
+  double* h_off64 = nullptr;     // [nslots] H = (A + A^T)/2
+  double* s_off64 = nullptr;     // [nslots] S = (A - A^T)/2
+  double* h_diag64 = nullptr;    // [npad]
+  __half* h_off16 = nullptr;
+  __half* s_off16 = nullptr;
+  __half* h_diag16 = nullptr;
+  float* h_off32 = nullptr;
+  float* s_off32 = nullptr;
+  float* h_diag32 = nullptr;
+
+  // solver workspace (lazily sized for the widest precision)
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  double* hist = nullptr;
+  int hist_cap = 0;
+  int hist_len = 0;
+  SyncState* sync = nullptr;
+  unsigned long long* flags = nullptr;  // [kMaxBlocks * kFlagStride]
+  double* part = nullptr;    // [2][kMaxBlocks][4]
+  double* result = nullptr;  // [2][4]
+  DevInfo* info = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+}  // namespace gadi
+
+struct gadi_handle {
+  gadi::System sys;
+};
+
+namespace gadi {
+gadi_status ensure_workspace(System& s);
+void free_system(System& s);
+}  // namespace gadi

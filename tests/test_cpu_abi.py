@@ -1,0 +1,62 @@
+"""CPU-side checks of the C ABI: the library loads and exports what include/gadi.h declares."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gadi.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b(gadi_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("gadi_setup", "gadi_ir_solve", "gadi_ir_solve_batched", "gadi_predict_params",
+                 "gadi_features", "gadi_train_mlp", "gadi_destroy", "gadi_status_str"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2501_04229_amd as gadi
+    lib = ctypes.CDLL(gadi.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", gadi.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (gadi_[a-z0-9_]+)", out))
+    assert set(_declared()) <= exported
+
+
+def test_status_strings_and_defaults():
+    import paper_2501_04229_amd as gadi
+    assert gadi.status_str(0) == "ok"
+    assert gadi.status_str(4) == "diverged"
+    assert gadi.status_str(99) == "unknown status"
+    o = gadi.options("fp64")
+    assert o.prec == 0 and o.eps_inner == 1e-6
+    o = gadi.options("fp16")
+    assert o.prec == 1 and 0 < o.eps_inner < 1
+
+
+def test_library_is_built_for_gfx950():
+    import paper_2501_04229_amd as gadi
+    data = open(gadi.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+
+
+def test_argument_checks_without_gpu():
+    """Null handles and bad enums are rejected before any device call."""
+    import paper_2501_04229_amd as gadi
+    L = gadi.lib()
+    h = ctypes.c_void_p()
+    assert L.gadi_setup(None, 0, ctypes.byref(h)) == gadi.EINVAL
+    assert L.gadi_ir_solve(None, None, None, 0.5, 0.5, 1e-10, None, None) == gadi.EINVAL
+    assert L.gadi_destroy(None) == gadi.EINVAL
+    assert L.gadi_spmv(None, 0, 1.0, None, None) == gadi.EINVAL
