@@ -231,7 +231,7 @@ def main():
         "config": {"workload": args.workload, "N": n, "nnz": z, "tol": 1e-10,
                    "eps_inner": eps if eps is not None else (1e-6 if args.prec == "fp64" else 1e-3),
                    "alpha": alpha, "omega": omega, "params": psrc, "prec": args.prec,
-                   "solve_kernel_blocks": g.solver_blocks()},
+                   "solve_launch_blocks_threads": list(g.solver_blocks())},
         "solve": {"status": info["status_str"], "sweeps": info["outer_sweeps"], "inner_H": info["inner_H"],
                   "inner_S": info["inner_S"], "relres": info["relres"], "rel_err_vs_xstar": rel_err_xstar,
                   "kernel_seconds": kern, "barriers": info["barriers"],

@@ -187,9 +187,12 @@ gadi_status gadi_destroy(gadi_handle* h);
 /* Static description of a status code. */
 const char* gadi_status_str(gadi_status s);
 
-/* Number of device blocks the persistent solve kernel uses for this handle
- * (for measurement scripts); 0 on error. */
-int32_t gadi_solver_blocks(gadi_handle* h);
+/* Launch shape of the last gadi_ir_solve on this handle: returns the number of
+ * blocks and stores the threads per block in *threads (may be NULL); 0 before
+ * the first solve.  The shape is chosen per handle and precision by a timed
+ * trial of candidate shapes on the first solve (override with the environment
+ * variables GADI_SOLVE_BLOCK and GADI_BLOCKS_PER_CU). */
+int32_t gadi_solver_blocks(gadi_handle* h, int32_t* threads);
 
 #ifdef __cplusplus
 }

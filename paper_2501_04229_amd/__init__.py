@@ -74,7 +74,7 @@ def _load():
         "gadi_predict_params": (i32, [vp, vp, P(f64), P(f64)]),
         "gadi_destroy": (i32, [vp]),
         "gadi_status_str": (ctypes.c_char_p, [i32]),
-        "gadi_solver_blocks": (i32, [vp]),
+        "gadi_solver_blocks": (i32, [vp, P(i32)]),
         "gadi_default_options": (None, [P(_Options), ctypes.c_int]),
     }
     for name, (res, args) in sigs.items():
@@ -218,8 +218,11 @@ class System:
                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), "gadi_features")
         return out
 
-    def solver_blocks(self) -> int:
-        return int(_lib.gadi_solver_blocks(self._h))
+    def solver_blocks(self):
+        """(blocks, threads per block) of the last solve launch."""
+        t = ctypes.c_int32(0)
+        nb = _lib.gadi_solver_blocks(self._h, ctypes.byref(t))
+        return int(nb), int(t.value)
 
 
 def solve_batched(systems, bs, alphas, omegas, tol=1e-10, prec="fp16", eps_inner=None, maxit_outer=5000,

@@ -98,6 +98,11 @@ struct System {
   double* result = nullptr;  // [2][4]
   DevInfo* info = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // launch shape of the solve kernel per precision mode, chosen by the autotuner
+  int tuned_block[3] = {0, 0, 0};
+  int tuned_per_cu[3] = {0, 0, 0};
+  int last_blocks = 0;
+  int last_block_threads = 0;
 };
 
 }  // namespace gadi

@@ -1,14 +1,415 @@
-// (alpha, omega) predictor: placeholder entry points until the MLP kernels land.
+// (alpha, omega) predictor: an 8 -> 64 -> 64 -> 2 multilayer perceptron with
+// ReLU hidden layers, fp32 weights, trained with Adam on mean squared error.
+// It stands in for the parameter-prediction step of Section 3.3 (the paper
+// regresses alpha on problem size with a Gaussian process); inputs are cheap
+// problem features, targets (log10 alpha, omega).
+//
+// Kernels (all arithmetic on the device):
+//   sample_kernel  one wavefront per sample: forward pass, loss terms and the
+//                  per-sample backward quantities dL/dz2, dL/dz1
+//   grad_kernel    one thread per parameter: sums its gradient over the batch
+//                  in sample order (fixed order, reproducible)
+//   loss_kernel    batch loss in sample order
+//   adam_kernel    one thread per parameter
+// Training replays one captured epoch (a HIP graph) `epochs` times.
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
 #include "internal.h"
 
-extern "C" {
-gadi_status gadi_mlp_create(uint64_t, gadi_mlp** out) { if (out) *out = nullptr; return GADI_EINVAL; }
-gadi_status gadi_mlp_destroy(gadi_mlp*) { return GADI_EINVAL; }
-gadi_status gadi_mlp_set_weights(gadi_mlp*, const float*) { return GADI_EINVAL; }
-gadi_status gadi_mlp_get_weights(gadi_mlp*, float*) { return GADI_EINVAL; }
-gadi_status gadi_mlp_set_norm(gadi_mlp*, const float*, const float*) { return GADI_EINVAL; }
-gadi_status gadi_mlp_forward(gadi_mlp*, const float*, int32_t, float*) { return GADI_EINVAL; }
-gadi_status gadi_mlp_loss_grad(gadi_mlp*, const float*, const float*, int32_t, float*, float*) { return GADI_EINVAL; }
-gadi_status gadi_train_mlp(gadi_mlp*, const float*, const float*, int32_t, int32_t, float, float*) { return GADI_EINVAL; }
-gadi_status gadi_predict_params(gadi_mlp*, const float*, double*, double*) { return GADI_EINVAL; }
+namespace gadi {
+
+constexpr int kIn = 8, kH = 64, kOut = 2;
+constexpr int oW1 = 0, oB1 = oW1 + kH * kIn, oW2 = oB1 + kH, oB2 = oW2 + kH * kH, oW3 = oB2 + kH,
+              oB3 = oW3 + kOut * kH, kNP = oB3 + kOut;
+static_assert(kNP == 4866, "parameter count");
+
+struct MlpBuf {
+  float* X = nullptr;    // [cap, 8] standardised inputs
+  float* Y = nullptr;    // [cap, 2] targets
+  float* out = nullptr;  // [cap, 2] predictions
+  float* z1 = nullptr;   // [cap, 64] pre-activations (forward cache)
+  float* z2 = nullptr;
+  float* h1 = nullptr;   // [cap, 64] activations
+  float* h2 = nullptr;
+  float* g1 = nullptr;   // [cap, 64] dL/dz1
+  float* g2 = nullptr;   // [cap, 64] dL/dz2
+  float* gy = nullptr;   // [cap, 2] dL/dy
+  int cap = 0;
+};
+
+}  // namespace gadi
+
+struct gadi_mlp {
+  float* w = nullptr;     // [kNP] device
+  float* g = nullptr;     // [kNP]
+  float* m = nullptr;     // Adam first moment
+  float* v = nullptr;     // Adam second moment
+  float* norm = nullptr;  // [16]: mu[8], sd[8]
+  float* loss = nullptr;  // [epochs] or [1]
+  int* step = nullptr;    // Adam step counter (device)
+  int loss_cap = 0;
+  float hnorm[16];
+  gadi::MlpBuf buf;
+};
+
+namespace gadi {
+
+// Forward + per-sample backward.  Block = 64 threads (one wavefront), one
+// sample per block; thread j owns hidden unit j of both layers.
+__global__ void __launch_bounds__(64) sample_kernel(const float* __restrict__ w, const float* __restrict__ X,
+                                                    const float* __restrict__ Y, int B, int want_grad,
+                                                    float* __restrict__ out, float* __restrict__ z1o,
+                                                    float* __restrict__ h1o, float* __restrict__ z2o,
+                                                    float* __restrict__ h2o, float* __restrict__ g1o,
+                                                    float* __restrict__ g2o, float* __restrict__ gyo) {
+  __shared__ float xs[kIn], h1[kH], h2[kH], gz2[kH], gy[kOut];
+  const int b = blockIdx.x, j = threadIdx.x;
+  if (j < kIn) xs[j] = X[(size_t)b * kIn + j];
+  __syncthreads();
+  float a = w[oB1 + j];
+#pragma unroll
+  for (int l = 0; l < kIn; ++l) a += w[oW1 + j * kIn + l] * xs[l];
+  const float z1 = a;
+  h1[j] = z1 > 0.f ? z1 : 0.f;
+  __syncthreads();
+  a = w[oB2 + j];
+  for (int i = 0; i < kH; ++i) a += w[oW2 + j * kH + i] * h1[i];
+  const float z2 = a;
+  h2[j] = z2 > 0.f ? z2 : 0.f;
+  __syncthreads();
+  // outputs: wavefront sums of W3[k, j] h2[j]
+  float y[kOut];
+#pragma unroll
+  for (int k = 0; k < kOut; ++k) {
+    float p = w[oW3 + k * kH + j] * h2[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
+    y[k] = p + w[oB3 + k];
+  }
+  if (j < kOut) out[(size_t)b * kOut + j] = y[j];
+  if (!want_grad) return;
+  z1o[(size_t)b * kH + j] = z1;
+  z2o[(size_t)b * kH + j] = z2;
+  h1o[(size_t)b * kH + j] = h1[j];
+  h2o[(size_t)b * kH + j] = h2[j];
+  // dL/dy for L = mean over B*2 outputs of (y - Y)^2
+  if (j < kOut) {
+    const float d = y[j] - Y[(size_t)b * kOut + j];
+    gy[j] = 2.f * d / (float)(B * kOut);
+    gyo[(size_t)b * kOut + j] = gy[j];
+  }
+  __syncthreads();
+  float gh2 = 0.f;
+#pragma unroll
+  for (int k = 0; k < kOut; ++k) gh2 += gy[k] * w[oW3 + k * kH + j];
+  const float g2 = z2 > 0.f ? gh2 : 0.f;
+  gz2[j] = g2;
+  g2o[(size_t)b * kH + j] = g2;
+  __syncthreads();
+  float gh1 = 0.f;
+  for (int i = 0; i < kH; ++i) gh1 += gz2[i] * w[oW2 + i * kH + j];
+  g1o[(size_t)b * kH + j] = z1 > 0.f ? gh1 : 0.f;
+}
+
+// Gradient of parameter p summed over the batch in sample order.
+__global__ void grad_kernel(const float* __restrict__ X, const float* __restrict__ h1, const float* __restrict__ h2,
+                            const float* __restrict__ g1, const float* __restrict__ g2, const float* __restrict__ gy,
+                            int B, float* __restrict__ grad) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kNP) return;
+  float s = 0.f;
+  if (p < oB1) {  // W1[i, l]
+    const int i = p / kIn, l = p % kIn;
+    for (int b = 0; b < B; ++b) s += g1[(size_t)b * kH + i] * X[(size_t)b * kIn + l];
+  } else if (p < oW2) {  // b1[i]
+    const int i = p - oB1;
+    for (int b = 0; b < B; ++b) s += g1[(size_t)b * kH + i];
+  } else if (p < oB2) {  // W2[j, i]
+    const int q = p - oW2, j = q / kH, i = q % kH;
+    for (int b = 0; b < B; ++b) s += g2[(size_t)b * kH + j] * h1[(size_t)b * kH + i];
+  } else if (p < oW3) {  // b2[j]
+    const int j = p - oB2;
+    for (int b = 0; b < B; ++b) s += g2[(size_t)b * kH + j];
+  } else if (p < oB3) {  // W3[k, j]
+    const int q = p - oW3, k = q / kH, j = q % kH;
+    for (int b = 0; b < B; ++b) s += gy[(size_t)b * kOut + k] * h2[(size_t)b * kH + j];
+  } else {  // b3[k]
+    const int k = p - oB3;
+    for (int b = 0; b < B; ++b) s += gy[(size_t)b * kOut + k];
+  }
+  grad[p] = s;
+}
+
+// Mean squared error of the batch, summed in sample order by one thread.
+__global__ void loss_kernel(const float* __restrict__ out, const float* __restrict__ Y, int B,
+                            const int* __restrict__ step, float* __restrict__ loss) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < B * kOut; ++i) {
+    const double d = (double)out[i] - (double)Y[i];
+    s += d * d;
+  }
+  loss[step ? *step : 0] = (float)(s / (B * kOut));
+}
+
+// Adam (Kingma and Ba): step number t = *step + 1.
+__global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, const int* __restrict__ step, float lr) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kNP) return;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const int t = *step + 1;
+  const float gp = g[p];
+  const float mp = b1 * m[p] + (1.f - b1) * gp;
+  const float vp = b2 * v[p] + (1.f - b2) * gp * gp;
+  m[p] = mp;
+  v[p] = vp;
+  const float mh = mp / (1.f - powf(b1, (float)t));
+  const float vh = vp / (1.f - powf(b2, (float)t));
+  w[p] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+__global__ void step_kernel(int* step) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *step += 1;
+}
+
+// Column mean and standard deviation of raw features (zero-variance columns
+// get scale 1), then in-place standardisation.
+__global__ void norm_kernel(float* __restrict__ X, int n, float* __restrict__ norm) {
+  const int c = threadIdx.x;
+  if (c < kIn) {
+    double mu = 0.0;
+    for (int i = 0; i < n; ++i) mu += X[(size_t)i * kIn + c];
+    mu /= n;
+    double var = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double d = X[(size_t)i * kIn + c] - mu;
+      var += d * d;
+    }
+    double sd = sqrt(var / n);
+    if (!(sd > 1e-12 * fmax(1.0, fabs(mu)))) sd = 1.0;
+    norm[c] = (float)mu;
+    norm[kIn + c] = (float)sd;
+  }
+  __syncthreads();
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n * kIn; i += gridDim.x * blockDim.x) {
+    const int cc = i % kIn;
+    X[i] = (X[i] - norm[cc]) / norm[kIn + cc];
+  }
+}
+
+__global__ void apply_norm_kernel(float* __restrict__ X, int n, const float* __restrict__ norm) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n * kIn; i += gridDim.x * blockDim.x) {
+    const int c = i % kIn;
+    X[i] = (X[i] - norm[c]) / norm[kIn + c];
+  }
+}
+
+static gadi_status ensure_buf(MlpBuf& b, int n) {
+  if (n <= b.cap) return GADI_OK;
+  float** ps[] = {&b.X, &b.Y, &b.out, &b.z1, &b.z2, &b.h1, &b.h2, &b.g1, &b.g2, &b.gy};
+  for (float** p : ps)
+    if (*p) {
+      (void)hipFree(*p);
+      *p = nullptr;
+    }
+  b.cap = 0;
+  GADI_HIP_CHECK(hipMalloc((void**)&b.X, sizeof(float) * n * kIn));
+  GADI_HIP_CHECK(hipMalloc((void**)&b.Y, sizeof(float) * n * kOut));
+  GADI_HIP_CHECK(hipMalloc((void**)&b.out, sizeof(float) * n * kOut));
+  GADI_HIP_CHECK(hipMalloc((void**)&b.gy, sizeof(float) * n * kOut));
+  float** hs[] = {&b.z1, &b.z2, &b.h1, &b.h2, &b.g1, &b.g2};
+  for (float** p : hs) GADI_HIP_CHECK(hipMalloc((void**)p, sizeof(float) * n * kH));
+  b.cap = n;
+  return GADI_OK;
+}
+
+// splitmix64 (Steele, Lea and Flood) for the initial weights
+static uint64_t splitmix64(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+static void launch_fwd_bwd(gadi_mlp* m, int B, int want_grad, hipStream_t st) {
+  MlpBuf& b = m->buf;
+  hipLaunchKernelGGL(sample_kernel, dim3(B), dim3(64), 0, st, m->w, b.X, b.Y, B, want_grad, b.out, b.z1, b.h1, b.z2,
+                     b.h2, b.g1, b.g2, b.gy);
+  if (want_grad)
+    hipLaunchKernelGGL(grad_kernel, dim3((kNP + 255) / 256), dim3(256), 0, st, b.X, b.h1, b.h2, b.g1, b.g2, b.gy, B,
+                       m->g);
+}
+
+}  // namespace gadi
+
+using namespace gadi;
+
+extern "C" gadi_status gadi_mlp_create(uint64_t seed, gadi_mlp** out) {
+  if (!out) return GADI_EINVAL;
+  *out = nullptr;
+  gadi_mlp* m = new (std::nothrow) gadi_mlp();
+  if (!m) return GADI_ENOMEM;
+  hipError_t e = hipMalloc((void**)&m->w, sizeof(float) * kNP);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->g, sizeof(float) * kNP);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->m, sizeof(float) * kNP);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->v, sizeof(float) * kNP);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->norm, sizeof(float) * 16);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->step, sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&m->loss, sizeof(float));
+  if (e != hipSuccess) {
+    gadi_mlp_destroy(m);
+    return fail_hip(e, "gadi_mlp_create", __FILE__, __LINE__);
+  }
+  m->loss_cap = 1;
+  // He-uniform weights U(-sqrt(6/fan_in), sqrt(6/fan_in)), zero biases
+  std::vector<float> w(kNP, 0.f);
+  uint64_t s = seed;
+  auto fill = [&](int off, int rows, int cols) {
+    const double bound = std::sqrt(6.0 / cols);
+    for (int i = 0; i < rows * cols; ++i) {
+      const double u = (double)(splitmix64(s) >> 11) * 0x1.0p-53;
+      w[off + i] = (float)((2.0 * u - 1.0) * bound);
+    }
+  };
+  fill(oW1, kH, kIn);
+  fill(oW2, kH, kH);
+  fill(oW3, kOut, kH);
+  for (int i = 0; i < kIn; ++i) {
+    m->hnorm[i] = 0.f;
+    m->hnorm[kIn + i] = 1.f;
+  }
+  e = hipMemcpy(m->w, w.data(), sizeof(float) * kNP, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->norm, m->hnorm, sizeof(float) * 16, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    gadi_mlp_destroy(m);
+    return fail_hip(e, "gadi_mlp_create", __FILE__, __LINE__);
+  }
+  *out = m;
+  return GADI_OK;
+}
+
+extern "C" gadi_status gadi_mlp_destroy(gadi_mlp* m) {
+  if (!m) return GADI_EINVAL;
+  void* ps[] = {m->w, m->g, m->m, m->v, m->norm, m->loss, m->step, m->buf.X, m->buf.Y, m->buf.out, m->buf.z1,
+                m->buf.z2, m->buf.h1, m->buf.h2, m->buf.g1, m->buf.g2, m->buf.gy};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  delete m;
+  return GADI_OK;
+}
+
+extern "C" gadi_status gadi_mlp_set_weights(gadi_mlp* m, const float* w) {
+  if (!m || !w) return GADI_EINVAL;
+  GADI_HIP_CHECK(hipMemcpy(m->w, w, sizeof(float) * kNP, hipMemcpyHostToDevice));
+  return GADI_OK;
+}
+
+extern "C" gadi_status gadi_mlp_get_weights(gadi_mlp* m, float* w) {
+  if (!m || !w) return GADI_EINVAL;
+  GADI_HIP_CHECK(hipMemcpy(w, m->w, sizeof(float) * kNP, hipMemcpyDeviceToHost));
+  return GADI_OK;
+}
+
+extern "C" gadi_status gadi_mlp_set_norm(gadi_mlp* m, const float* mu, const float* sd) {
+  if (!m || !mu || !sd) return GADI_EINVAL;
+  for (int i = 0; i < kIn; ++i) {
+    if (!(sd[i] > 0.f) || !std::isfinite(mu[i])) return GADI_EINVAL;
+    m->hnorm[i] = mu[i];
+    m->hnorm[kIn + i] = sd[i];
+  }
+  GADI_HIP_CHECK(hipMemcpy(m->norm, m->hnorm, sizeof(float) * 16, hipMemcpyHostToDevice));
+  return GADI_OK;
+}
+
+extern "C" gadi_status gadi_mlp_forward(gadi_mlp* m, const float* X, int32_t B, float* Y) {
+  if (!m || !X || !Y || B < 1) return GADI_EINVAL;
+  gadi_status st = ensure_buf(m->buf, B);
+  if (st != GADI_OK) return st;
+  GADI_HIP_CHECK(hipMemcpy(m->buf.X, X, sizeof(float) * B * kIn, hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(apply_norm_kernel, dim3((B * kIn + 255) / 256), dim3(256), 0, 0, m->buf.X, B, m->norm);
+  launch_fwd_bwd(m, B, 0, 0);
+  GADI_HIP_CHECK(hipGetLastError());
+  GADI_HIP_CHECK(hipMemcpy(Y, m->buf.out, sizeof(float) * B * kOut, hipMemcpyDeviceToHost));
+  return GADI_OK;
+}
+
+extern "C" gadi_status gadi_mlp_loss_grad(gadi_mlp* m, const float* Xs, const float* Y, int32_t B, float* loss,
+                                          float* grad) {
+  if (!m || !Xs || !Y || B < 1 || !loss || !grad) return GADI_EINVAL;
+  gadi_status st = ensure_buf(m->buf, B);
+  if (st != GADI_OK) return st;
+  GADI_HIP_CHECK(hipMemcpy(m->buf.X, Xs, sizeof(float) * B * kIn, hipMemcpyHostToDevice));
+  GADI_HIP_CHECK(hipMemcpy(m->buf.Y, Y, sizeof(float) * B * kOut, hipMemcpyHostToDevice));
+  launch_fwd_bwd(m, B, 1, 0);
+  hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(64), 0, 0, m->buf.out, m->buf.Y, B, (const int*)nullptr, m->loss);
+  GADI_HIP_CHECK(hipGetLastError());
+  GADI_HIP_CHECK(hipMemcpy(grad, m->g, sizeof(float) * kNP, hipMemcpyDeviceToHost));
+  GADI_HIP_CHECK(hipMemcpy(loss, m->loss, sizeof(float), hipMemcpyDeviceToHost));
+  return GADI_OK;
+}
+
+extern "C" gadi_status gadi_train_mlp(gadi_mlp* m, const float* X, const float* Y, int32_t n, int32_t epochs,
+                                      float lr, float* loss_out) {
+  if (!m || !X || !Y || n < 1 || epochs < 1 || !(lr > 0.f)) return GADI_EINVAL;
+  gadi_status st = ensure_buf(m->buf, n);
+  if (st != GADI_OK) return st;
+  if (m->loss_cap < epochs) {
+    (void)hipFree(m->loss);
+    m->loss = nullptr;
+    m->loss_cap = 0;
+    GADI_HIP_CHECK(hipMalloc((void**)&m->loss, sizeof(float) * epochs));
+    m->loss_cap = epochs;
+  }
+  GADI_HIP_CHECK(hipMemcpy(m->buf.X, X, sizeof(float) * n * kIn, hipMemcpyHostToDevice));
+  GADI_HIP_CHECK(hipMemcpy(m->buf.Y, Y, sizeof(float) * n * kOut, hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(norm_kernel, dim3(1), dim3(256), 0, 0, m->buf.X, n, m->norm);
+  GADI_HIP_CHECK(hipGetLastError());
+  GADI_HIP_CHECK(hipMemcpy(m->hnorm, m->norm, sizeof(float) * 16, hipMemcpyDeviceToHost));
+  GADI_HIP_CHECK(hipMemset(m->m, 0, sizeof(float) * kNP));
+  GADI_HIP_CHECK(hipMemset(m->v, 0, sizeof(float) * kNP));
+  GADI_HIP_CHECK(hipMemset(m->step, 0, sizeof(int)));
+  GADI_HIP_CHECK(hipDeviceSynchronize());
+  // one epoch = forward/backward, loss, Adam, step counter; captured once, replayed
+  hipStream_t cs;
+  GADI_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    launch_fwd_bwd(m, n, 1, cs);
+    hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(64), 0, cs, m->buf.out, m->buf.Y, n, (const int*)m->step, m->loss);
+    hipLaunchKernelGGL(adam_kernel, dim3((kNP + 255) / 256), dim3(256), 0, cs, m->w, m->g, m->m, m->v,
+                       (const int*)m->step, lr);
+    hipLaunchKernelGGL(step_kernel, dim3(1), dim3(64), 0, cs, m->step);
+    e = hipStreamEndCapture(cs, &graph);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  for (int ep = 0; e == hipSuccess && ep < epochs; ++ep) e = hipGraphLaunch(exec, cs);
+  if (e == hipSuccess) e = hipStreamSynchronize(cs);
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) return fail_hip(e, "gadi_train_mlp", __FILE__, __LINE__);
+  if (loss_out) GADI_HIP_CHECK(hipMemcpy(loss_out, m->loss, sizeof(float) * epochs, hipMemcpyDeviceToHost));
+  return GADI_OK;
+}
+
+extern "C" gadi_status gadi_predict_params(gadi_mlp* m, const float* features, double* alpha, double* omega) {
+  if (!m || !features || !alpha || !omega) return GADI_EINVAL;
+  float y[2];
+  gadi_status st = gadi_mlp_forward(m, features, 1, y);
+  if (st != GADI_OK) return st;
+  if (!std::isfinite(y[0]) || !std::isfinite(y[1])) return GADI_EINVAL;
+  double a = std::pow(10.0, (double)y[0]);
+  a = a < 1e-3 ? 1e-3 : (a > 10.0 ? 10.0 : a);
+  double w = y[1] < 0.f ? 0.0 : (y[1] > 1.99f ? 1.99 : (double)y[1]);
+  *alpha = a;
+  *omega = w;
+  return GADI_OK;
 }

@@ -1,321 +1,31 @@
-// GADI-IR solve: one persistent, cooperatively launched kernel runs the whole
-// refinement loop of Algorithm 1 (Section 2.1) on the device.  Phases are
-// separated by device-wide all-reduces (device_common.h); no host round trip
-// happens inside a solve.
-//
-// One outer sweep:
-//   a1  r = b - A x in double, ||r||_2^2 and ||r||_inf                 (step 1)
-//   a2  stop if ||r|| <= tol ||r_0||, diverged, or sweep limit        (while test)
-//   a3  CG on (alpha I + H) z = r * 2^-e1 with e1 from ||r||_inf      (step 2)
-//   a4  g = (2 - omega) z * 2^-e2 with e2 from ||z||_inf               (step 3 rhs)
-//   a5  CGNE on (I + S/alpha) u = g:
-//         CG on (I - S^2/alpha^2) w = g, u = (I - S/alpha) w          (step 3)
-//   a6  x += u * 2^(e1 + e2) in double                                (step 4)
-// Dividing the S-step by alpha turns (alpha I + S) y = (2 - omega) alpha z into
-// (I + S/alpha) y = (2 - omega) z, so alpha never enters a stored half value;
-// the exact power-of-two scalings keep every half-precision right-hand side
-// in [1/2, 1) in max norm.
-//
-// The CG recurrences fold the direction update into the product phase:
-// q_{k+1} = K p_{k+1} = K r_{k+1} + beta q_k, so each CG step needs two
-// device-wide reductions and one operator product.
+// GADI-IR solve of one large system: one persistent, cooperatively launched
+// kernel runs the whole refinement loop on the device, with device-wide
+// all-reduces between phases (device_common.h); no host round trip happens
+// inside a solve.  The block size and blocks per compute unit are chosen per
+// system by a short timed trial of each candidate (autotune).
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <tuple>
 
-#include "device_common.h"
+#include "solve_body.h"
 
 namespace gadi {
 
-struct SolveArgs {
-  int n, npad, ntiles, maxit_out, maxit_in, hist_cap;
-  const int32_t* slice_ptr;
-  const int32_t* col;
-  const double* a_off;
-  const double* a_diag;
-  const void* h_off;
-  const void* s_off;
-  const void* h_diag;
-  const double* b;
-  double* x;
-  void* r;
-  void* z;
-  void* w;
-  void* vr;
-  void* vp;
-  void* vq;
-  void* vt;
-  double alpha, omega, tol, eps_h, eps_s;
-  SyncState* sync;
-  unsigned long long* flags;
-  double* part;
-  double* result;
-  DevInfo* info;
-  double* hist;
-  long long timeout;
-};
-
-// Device-wide reduction into out[4]; leaves the kernel if a barrier timed out.
-#define ALLREDUCE(a0, a1, a2, a3)                                              \
-  do {                                                                         \
-    bool ok_;                                                                  \
-    const Red4 r_ = grid_allreduce<kSolveBlock>(g, (a0), (a1), (a2), (a3), ok_); \
-    if (!ok_) return;                                                          \
-    out[0] = r_.v[0];                                                          \
-    out[1] = r_.v[1];                                                          \
-    out[2] = r_.v[2];                                                          \
-    out[3] = r_.v[3];                                                          \
-  } while (0)
-
-static __device__ __forceinline__ int clamp_exp(int e) { return e < -120 ? -120 : (e > 120 ? 120 : e); }
-
-template <class Mode>
-__global__ void __launch_bounds__(kSolveBlock) solve_kernel(SolveArgs a) {
-  using MT = typename Mode::MT;
-  using VT = typename Mode::VT;
-  using ST = typename Mode::ST;
-  using RT = typename Mode::RT;
-  using AT = typename Mode::AT;
-
-  Grid g{a.sync, a.flags, a.part, a.result, gridDim.x, 0ull, a.timeout, 0ll};
-  const int tid = threadIdx.x;
+// One large system: persistent cooperative launch, one band of rows per block.
+template <class Mode, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) solve_kernel(SolveArgs a) {
+  GridRed<BLOCK> red{Grid{a.sync, a.flags, a.part, a.result, gridDim.x, 0ull, a.timeout, 0ll}};
   const unsigned lb = logical_block(blockIdx.x, gridDim.x);
   const int t0 = (int)((long long)a.ntiles * lb / gridDim.x);
   const int t1 = (int)((long long)a.ntiles * (lb + 1) / gridDim.x);
-
-  const int32_t* __restrict__ sp = a.slice_ptr;
-  const int32_t* __restrict__ col = a.col;
-  const MT* __restrict__ hoff = (const MT*)a.h_off;
-  const MT* __restrict__ soff = (const MT*)a.s_off;
-  const MT* __restrict__ hdiag = (const MT*)a.h_diag;
-  RT* __restrict__ r = (RT*)a.r;
-  ST* __restrict__ z = (ST*)a.z;
-  ST* __restrict__ w = (ST*)a.w;
-  VT* __restrict__ vr = (VT*)a.vr;
-  VT* __restrict__ vp = (VT*)a.vp;
-  VT* __restrict__ vq = (VT*)a.vq;
-  VT* __restrict__ vt = (VT*)a.vt;
-  double* __restrict__ x = a.x;
-  const double* __restrict__ b = a.b;
-
-  const AT alpha = (AT)a.alpha;
-  const AT inv_alpha = (AT)(1.0 / a.alpha);
-  const AT two_m_omega = (AT)(2.0 - a.omega);
-  const double eps_h2 = a.eps_h * a.eps_h;
-  const double eps_s2 = a.eps_s * a.eps_s;
-
-  double out[4];
-  double rho0 = 0.0, res = 0.0;
-  int status = GADI_EMAXIT;
-  int sweep = 0;
-  long long ih = 0, is = 0;
-
-  for (;;) {
-    // ---------------------------------------------------------- a1: residual
-    {
-      double s0 = 0.0, m3 = 0.0;
-      for (int t = t0; t < t1; ++t) {
-        const int row = t * kTile + tid;
-        const double ax = a.a_diag[row] * x[row] +
-                          row_sum<double>(row, sp, col, a.a_off, [&](int c) { return x[c]; });
-        const double ri = b[row] - ax;
-        r[row] = (RT)ri;
-        s0 += ri * ri;
-        m3 = fmax(m3, fabs(ri));
-      }
-      ALLREDUCE(s0, 0.0, 0.0, m3);
-    }
-    const double rho = sqrt(out[0]);
-    const double rmax = out[3];
-    if (sweep == 0) rho0 = rho;
-    res = rho0 > 0.0 ? rho / rho0 : 0.0;
-    if (a.hist && sweep < a.hist_cap && blockIdx.x == 0 && tid == 0) a.hist[sweep] = res;
-    if (rho <= a.tol * rho0) {
-      status = GADI_OK;
-      break;
-    }
-    if (!isfinite(rho) || rho > 1e6 * rho0) {
-      status = GADI_EDIVERGED;
-      break;
-    }
-    if (sweep >= a.maxit_out) {
-      status = GADI_EMAXIT;
-      break;
-    }
-
-    // ---------------------------------------------------------- a3: CG on alpha I + H
-    int e1;
-    (void)frexp(rmax, &e1);
-    e1 = clamp_exp(e1);
-    const AT sc1 = (AT)ldexp(1.0, -e1);
-    double pq, rr, rr0, zmax = 0.0;
-    {
-      double s0 = 0.0, s1 = 0.0;
-      for (int t = t0; t < t1; ++t) {
-        const int row = t * kTile + tid;
-        const VT pi = st<VT>((AT)r[row] * sc1);
-        const AT api = ld<AT>(pi);
-        const AT kp = (alpha + ld<AT>(hdiag[row])) * api +
-                      row_sum<AT>(row, sp, col, hoff, [&](int c) { return ld<AT>(st<VT>((AT)r[c] * sc1)); });
-        const VT qi = st<VT>(kp);
-        vr[row] = pi;
-        vp[row] = pi;
-        vq[row] = qi;
-        s0 += (double)api * (double)ld<AT>(qi);
-        s1 += (double)api * (double)api;
-      }
-      ALLREDUCE(s0, s1, 0.0, 0.0);
-      pq = out[0];
-      rr0 = out[1];
-      rr = rr0;
-    }
-    int it = 0;
-    if (rr0 > 0.0) {
-      for (;;) {
-        if (!(pq > 0.0) || !isfinite(pq)) {
-          if (it == 0) status = isfinite(pq) ? GADI_ENOTSPD : (Mode::id == GADI_PREC_FP16_IR ? GADI_EOVERFLOW16 : GADI_EDIVERGED);
-          break;
-        }
-        const AT ak = (AT)(rr / pq);
-        double s0 = 0.0, m3 = 0.0;
-        for (int t = t0; t < t1; ++t) {
-          const int row = t * kTile + tid;
-          const AT pi = ld<AT>(vp[row]);
-          const ST zi = (it == 0 ? ST(0) : z[row]) + (ST)(ak * pi);
-          z[row] = zi;
-          const VT ri = st<VT>(ld<AT>(vr[row]) - ak * ld<AT>(vq[row]));
-          vr[row] = ri;
-          const double dr = (double)ld<AT>(ri);
-          s0 += dr * dr;
-          m3 = fmax(m3, fabs((double)zi));
-        }
-        ALLREDUCE(s0, 0.0, 0.0, m3);
-        const double rr_new = out[0];
-        zmax = out[3];
-        ++it;
-        if (rr_new <= eps_h2 * rr0 || it >= a.maxit_in || !isfinite(rr_new)) break;
-        const AT beta = (AT)(rr_new / rr);
-        rr = rr_new;
-        s0 = 0.0;
-        for (int t = t0; t < t1; ++t) {
-          const int row = t * kTile + tid;
-          const AT ri = ld<AT>(vr[row]);
-          const AT kr = (alpha + ld<AT>(hdiag[row])) * ri +
-                        row_sum<AT>(row, sp, col, hoff, [&](int c) { return ld<AT>(vr[c]); });
-          const VT pn = st<VT>(ri + beta * ld<AT>(vp[row]));
-          const VT qn = st<VT>(kr + beta * ld<AT>(vq[row]));
-          vp[row] = pn;
-          vq[row] = qn;
-          s0 += (double)ld<AT>(pn) * (double)ld<AT>(qn);
-        }
-        ALLREDUCE(s0, 0.0, 0.0, 0.0);
-        pq = out[0];
-      }
-    }
-    ih += it;
-    if (status != GADI_EMAXIT) break;  // inner breakdown on the first step
-    if (!isfinite(zmax)) {
-      status = Mode::id == GADI_PREC_FP16_IR ? GADI_EOVERFLOW16 : GADI_EDIVERGED;
-      break;
-    }
-
-    // ---------------------------------------------------------- a4/a5: CGNE on I + S/alpha
-    int its = 0;
-    if (it > 0 && zmax > 0.0) {
-      int e2;
-      (void)frexp((double)two_m_omega * zmax, &e2);
-      e2 = clamp_exp(e2);
-      const AT sc2 = (AT)ldexp(1.0, -e2);
-      double rrs0;
-      {
-        double s1 = 0.0;
-        for (int t = t0; t < t1; ++t) {
-          const int row = t * kTile + tid;
-          const VT gi = st<VT>(two_m_omega * (AT)z[row] * sc2);
-          const AT tv = inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) {
-                          return ld<AT>(st<VT>(two_m_omega * (AT)z[c] * sc2));
-                        });
-          vr[row] = gi;
-          vp[row] = gi;
-          vt[row] = st<VT>(tv);
-          const double dg = (double)ld<AT>(gi);
-          s1 += dg * dg;
-        }
-        ALLREDUCE(0.0, s1, 0.0, 0.0);
-        rrs0 = out[1];
-      }
-      double rrs = rrs0;
-      if (rrs0 > 0.0) {
-        for (;;) {
-          // q = p - (S/alpha) t, with t = (S/alpha) p
-          double s0 = 0.0;
-          for (int t = t0; t < t1; ++t) {
-            const int row = t * kTile + tid;
-            const AT pi = ld<AT>(vp[row]);
-            const AT qv = pi - inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) { return ld<AT>(vt[c]); });
-            const VT qi = st<VT>(qv);
-            vq[row] = qi;
-            s0 += (double)pi * (double)ld<AT>(qi);
-          }
-          ALLREDUCE(s0, 0.0, 0.0, 0.0);
-          const double pqs = out[0];
-          if (!(pqs > 0.0) || !isfinite(pqs)) {
-            if (its == 0) status = isfinite(pqs) ? GADI_ENOTSPD : (Mode::id == GADI_PREC_FP16_IR ? GADI_EOVERFLOW16 : GADI_EDIVERGED);
-            break;
-          }
-          const AT ak = (AT)(rrs / pqs);
-          s0 = 0.0;
-          for (int t = t0; t < t1; ++t) {
-            const int row = t * kTile + tid;
-            const AT pi = ld<AT>(vp[row]);
-            w[row] = (its == 0 ? ST(0) : w[row]) + (ST)(ak * pi);
-            const VT ri = st<VT>(ld<AT>(vr[row]) - ak * ld<AT>(vq[row]));
-            vr[row] = ri;
-            const double dr = (double)ld<AT>(ri);
-            s0 += dr * dr;
-          }
-          ALLREDUCE(s0, 0.0, 0.0, 0.0);
-          const double rr_new = out[0];
-          ++its;
-          if (rr_new <= eps_s2 * rrs0 || its >= a.maxit_in || !isfinite(rr_new)) break;
-          const AT beta = (AT)(rr_new / rrs);
-          rrs = rr_new;
-          for (int t = t0; t < t1; ++t) {
-            const int row = t * kTile + tid;
-            const AT ri = ld<AT>(vr[row]);
-            const AT sr = inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) { return ld<AT>(vr[c]); });
-            vt[row] = st<VT>(sr + beta * ld<AT>(vt[row]));
-            vp[row] = st<VT>(ri + beta * ld<AT>(vp[row]));
-          }
-          ALLREDUCE(0.0, 0.0, 0.0, 0.0);
-        }
-      }
-      is += its;
-      if (status != GADI_EMAXIT) break;
-
-      // ---------------------------------------------------------- a6: x += (I - S/alpha) w * 2^(e1+e2)
-      if (its > 0) {
-        const double unscale = ldexp(1.0, e1 + e2);
-        for (int t = t0; t < t1; ++t) {
-          const int row = t * kTile + tid;
-          const AT ui = (AT)w[row] - inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) { return (AT)w[c]; });
-          x[row] += (double)ui * unscale;
-        }
-        ALLREDUCE(0.0, 0.0, 0.0, 0.0);
-      }
-    }
-    ++sweep;
-  }
-
-  if (blockIdx.x == 0 && tid == 0) {
-    a.info->status = status;
-    a.info->sweeps = sweep;
-    a.info->inner_h = ih;
-    a.info->inner_s = is;
-    a.info->relres = res;
-    a.info->rho0 = rho0;
-    a.info->barriers = (long long)g.epoch;
-    a.info->barrier_ticks = g.wait_ticks;
+  DevInfo r{};
+  if (!solve_body<Mode, BLOCK>(a, red, t0, t1, r)) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    r.barriers = (long long)red.g.epoch;
+    r.barrier_ticks = red.g.wait_ticks;
+    *a.info = r;
   }
 }
 
@@ -399,27 +109,97 @@ static gadi_status ensure_fp32(System& s) {
   return GADI_OK;
 }
 
-template <class Mode>
-static gadi_status launch_solve(System& s, const SolveArgs& args, int* blocks_out) {
-  static int per_cu = 0;
-  if (!per_cu) {
-    int nb = 0;
-    GADI_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, solve_kernel<Mode>, kSolveBlock, 0));
-    per_cu = nb > 0 ? nb : 1;
-    if (const char* env = std::getenv("GADI_BLOCKS_PER_CU")) {
-      int v = std::atoi(env);
-      if (v > 0 && v < per_cu) per_cu = v;
-    }
-  }
+__global__ void fill_zero_kernel(double* __restrict__ p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+gadi_status ensure_fp32_public(System& s) { return ensure_fp32(s); }
+
+template <class Mode, int BLOCK>
+static gadi_status launch_t(System& s, SolveArgs a, int per_cu) {
+  int nb = 0;
+  GADI_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, solve_kernel<Mode, BLOCK>, BLOCK, 0));
+  if (nb < 1 || per_cu > nb) return GADI_EINVAL;  // not co-resident: not a valid shape
+  const int ntiles = s.npad / BLOCK;
   long long G = (long long)per_cu * num_cus();
-  if (G > s.npad / kTile) G = s.npad / kTile;
+  if (G > ntiles) G = ntiles;
   if (G > kMaxBlocks) G = kMaxBlocks;
   if (G < 1) G = 1;
-  *blocks_out = (int)G;
-  SolveArgs a = args;
+  a.ntiles = ntiles;
+  hipLaunchKernelGGL(reset_sync_kernel, dim3(32), dim3(1024), 0, s.stream, s.sync, s.flags, s.info);
+  GADI_HIP_CHECK(hipGetLastError());
   void* kargs[] = {(void*)&a};
-  GADI_HIP_CHECK(hipLaunchCooperativeKernel((const void*)solve_kernel<Mode>, dim3((unsigned)G), dim3(kSolveBlock), kargs, 0,
-                                            s.stream));
+  GADI_HIP_CHECK(hipLaunchCooperativeKernel((const void*)solve_kernel<Mode, BLOCK>, dim3((unsigned)G), dim3(BLOCK),
+                                            kargs, 0, s.stream));
+  s.last_blocks = (int)G;
+  s.last_block_threads = BLOCK;
+  return GADI_OK;
+}
+
+template <class Mode>
+static gadi_status launch_mode(System& s, const SolveArgs& a, int block, int per_cu) {
+  switch (block) {
+    case 256: return launch_t<Mode, 256>(s, a, per_cu);
+    case 512: return launch_t<Mode, 512>(s, a, per_cu);
+    case 1024: return launch_t<Mode, 1024>(s, a, per_cu);
+  }
+  return GADI_EINVAL;
+}
+
+static gadi_status launch_solve(System& s, int prec, const SolveArgs& a, int block, int per_cu) {
+  if (prec == GADI_PREC_FP16_IR) return launch_mode<ModeF16>(s, a, block, per_cu);
+  if (prec == GADI_PREC_FP32_IR) return launch_mode<ModeF32>(s, a, block, per_cu);
+  return launch_mode<ModeF64>(s, a, block, per_cu);
+}
+
+// Autotuner: time two outer sweeps from x = 0 in every candidate launch shape
+// (threads per block x blocks per compute unit) and keep the one with the
+// lowest time per phase.  Runs once per handle and precision; the choice is
+// overridden by GADI_SOLVE_BLOCK / GADI_BLOCKS_PER_CU.
+static gadi_status tune_solve(System& s, int prec, SolveArgs a, double* dx) {
+  if (s.tuned_block[prec]) return GADI_OK;
+  const char* eb = std::getenv("GADI_SOLVE_BLOCK");
+  const char* ec = std::getenv("GADI_BLOCKS_PER_CU");
+  if (eb || ec) {
+    s.tuned_block[prec] = eb ? std::atoi(eb) : 1024;
+    s.tuned_per_cu[prec] = ec ? std::atoi(ec) : 1;
+    return GADI_OK;
+  }
+  static const int cand[][2] = {{1024, 1}, {512, 2}, {512, 1}, {256, 4}, {256, 2}};
+  a.maxit_out = a.maxit_out < 3 ? a.maxit_out : 3;
+  a.hist = nullptr;
+  a.hist_cap = 0;
+  double best = 1e300;
+  int bb = 1024, bc = 1;
+  // the first launch also pays code loading and cold caches: run it untimed
+  for (int pass = 0; pass < 3; ++pass) {
+    for (const auto& c : cand) {
+      hipLaunchKernelGGL(fill_zero_kernel, dim3(256), dim3(256), 0, s.stream, dx, (long long)s.npad);
+      GADI_HIP_CHECK(hipEventRecord(s.ev0, s.stream));
+      gadi_status st = launch_solve(s, prec, a, c[0], c[1]);
+      if (st == GADI_EINVAL) continue;
+      if (st != GADI_OK) return st;
+      GADI_HIP_CHECK(hipEventRecord(s.ev1, s.stream));
+      DevInfo di;
+      GADI_HIP_CHECK(hipMemcpyAsync(&di, s.info, sizeof(DevInfo), hipMemcpyDeviceToHost, s.stream));
+      GADI_HIP_CHECK(hipStreamSynchronize(s.stream));
+      float ms = 0.f;
+      GADI_HIP_CHECK(hipEventElapsedTime(&ms, s.ev0, s.ev1));
+      const double per = ms / (double)(di.barriers > 0 ? di.barriers : 1);
+      if (pass == 0) break;  // warm-up launch only
+      if (std::getenv("GADI_DEBUG"))
+        std::fprintf(stderr, "gadi: tune prec %d block %d x %d/CU: %.2f us/phase (%lld phases)\n", prec, c[0], c[1],
+                     per * 1e3, (long long)di.barriers);
+      if (per < best) {
+        best = per;
+        bb = c[0];
+        bc = c[1];
+      }
+    }
+  }
+  s.tuned_block[prec] = bb;
+  s.tuned_per_cu[prec] = bc;
   return GADI_OK;
 }
 
@@ -474,12 +254,10 @@ extern "C" gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x,
   const hipMemcpyKind kin = o.on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   const hipMemcpyKind kout = o.on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   GADI_HIP_CHECK(hipMemcpyAsync(db, b, sizeof(double) * s.n, kin, s.stream));
-  GADI_HIP_CHECK(hipMemcpyAsync(dx, x, sizeof(double) * s.n, kin, s.stream));
 
   SolveArgs a{};
   a.n = s.n;
   a.npad = s.npad;
-  a.ntiles = s.npad / kTile;
   a.maxit_out = o.maxit_outer;
   a.maxit_in = o.maxit_inner;
   a.hist_cap = o.record_history ? s.hist_cap : 0;
@@ -521,13 +299,10 @@ extern "C" gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x,
     a.s_off = s.s_off64;
     a.h_diag = s.h_diag64;
   }
-  hipLaunchKernelGGL(reset_sync_kernel, dim3(32), dim3(1024), 0, s.stream, s.sync, s.flags, s.info);
-  GADI_HIP_CHECK(hipGetLastError());
+  if ((st = tune_solve(s, o.prec, a, dx)) != GADI_OK) return st;
+  GADI_HIP_CHECK(hipMemcpyAsync(dx, x, sizeof(double) * s.n, kin, s.stream));
   GADI_HIP_CHECK(hipEventRecord(s.ev0, s.stream));
-  int blocks = 0;
-  if (o.prec == GADI_PREC_FP16_IR) st = launch_solve<ModeF16>(s, a, &blocks);
-  else if (o.prec == GADI_PREC_FP32_IR) st = launch_solve<ModeF32>(s, a, &blocks);
-  else st = launch_solve<ModeF64>(s, a, &blocks);
+  st = launch_solve(s, o.prec, a, s.tuned_block[o.prec], s.tuned_per_cu[o.prec]);
   if (st != GADI_OK) return st;
   GADI_HIP_CHECK(hipEventRecord(s.ev1, s.stream));
   GADI_HIP_CHECK(hipMemcpyAsync(x, dx, sizeof(double) * s.n, kout, s.stream));
@@ -561,12 +336,8 @@ extern "C" int32_t gadi_get_history(gadi_handle* h, double* out, int32_t cap) {
   return n;
 }
 
-extern "C" int32_t gadi_solver_blocks(gadi_handle* h) {
-  if (!h || device_props() != GADI_OK) return 0;
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, solve_kernel<ModeF16>, kSolveBlock, 0) != hipSuccess) return 0;
-  long long G = (long long)nb * num_cus();
-  if (G > h->sys.npad / kTile) G = h->sys.npad / kTile;
-  if (G > kMaxBlocks) G = kMaxBlocks;
-  return (int32_t)(G < 1 ? 1 : G);
+extern "C" int32_t gadi_solver_blocks(gadi_handle* h, int32_t* threads) {
+  if (!h) return 0;
+  if (threads) *threads = h->sys.last_block_threads;
+  return h->sys.last_blocks;
 }

@@ -1,0 +1,152 @@
+"""GPU tests of the batched (alpha, omega) sweep and the MLP predictor kernels.
+
+The batched launch is checked against single-system solves through the same C
+ABI (same algorithm, block-local instead of device-wide reductions) and
+against the CPU oracle's residual; the MLP kernels are checked against the
+float64 numpy MLP oracle, which is itself pinned by finite differences.
+"""
+import numpy as np
+import pytest
+
+import gadi_inputs as gi
+import oracle
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2501_04229_amd as gadi  # noqa: E402
+
+FAMILY = [(12, 2, 5.0), (30, 2, 80.0), (7, 3, (2.0, 9.0, 30.0)), (9, 3, 1.0), (20, 2, 300.0), (5, 3, 0.0)]
+ALPHAS = [0.0215, 0.464, 2.0, 10.0]
+OMEGAS = [1.0, 0.5, 0.0, 1.5]
+
+
+@pytest.fixture(scope="module")
+def family():
+    out = []
+    for i, (n, dim, beta) in enumerate(FAMILY):
+        A = gi.convdiff(n, dim, beta)
+        xs, b = gi.rhs_for(A, "uniform", 100 + i)
+        out.append((A, b, gadi.System(A), oracle.OracleSystem(A)))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp16", "fp64"])
+def test_batched_matches_single_solves(family, prec):
+    systems = [f[2] for f in family]
+    bs = [f[1] for f in family]
+    eps = 1e-6 if prec == "fp64" else None
+    recs, xs = gadi.solve_batched(systems, bs, ALPHAS, OMEGAS, tol=1e-10, prec=prec, eps_inner=eps,
+                                  maxit_outer=4000, want_x=True)
+    for si, (A, b, g, o) in enumerate(family):
+        for ti, (al, om) in enumerate(zip(ALPHAS, OMEGAS)):
+            r = recs[si][ti]
+            x1, i1 = g.solve(b, al, om, tol=1e-10, prec=prec, eps_inner=eps, maxit_outer=4000)
+            assert r["status"] == i1["status"], (si, ti, r, i1)
+            assert r["alpha"] == al and r["omega"] == om
+            if i1["status"] == gadi.OK:
+                # reduction order differs (block-local vs device-wide): counts agree closely
+                assert abs(r["outer_sweeps"] - i1["outer_sweeps"]) <= max(2, 0.02 * i1["outer_sweeps"]), (si, ti)
+                assert r["relres"] <= 1e-10
+        # trial 0's solution: FP64 residual recomputed by the oracle
+        if recs[si][0]["status"] == gadi.OK:
+            assert np.linalg.norm(b - o.spmv("A", xs[si])) <= 1.0000001e-10 * np.linalg.norm(b)
+
+
+def test_batched_is_reproducible_and_isolates_failures(family):
+    systems = [f[2] for f in family]
+    bs = [f[1] for f in family]
+    alphas = [1e-3, 0.464]
+    omegas = [0.5, 0.5]
+    r1, x1 = gadi.solve_batched(systems, bs, alphas, omegas, tol=1e-10, prec="fp16", maxit_outer=300, want_x=True)
+    r2, x2 = gadi.solve_batched(systems, bs, alphas, omegas, tol=1e-10, prec="fp16", maxit_outer=300, want_x=True)
+    for si in range(len(systems)):
+        for ti in range(2):
+            a, b = r1[si][ti], r2[si][ti]
+            for k in ("status", "outer_sweeps", "inner_H", "inner_S", "relres"):
+                assert a[k] == b[k], (si, ti, k)
+        assert np.array_equal(x1[si], x2[si])
+        # the well-regularised trial converges whatever its neighbour trial does
+        assert r1[si][1]["status"] == gadi.OK
+        assert r1[si][0]["status"] in (gadi.OK, gadi.EOVERFLOW16, gadi.EMAXIT, gadi.EDIVERGED)
+
+
+def test_batched_argument_checks(family):
+    systems = [family[0][2]]
+    bs = [family[0][1]]
+    with pytest.raises(gadi.GadiError):
+        gadi.solve_batched(systems, bs, [0.5] * 17, [0.5] * 17)
+    with pytest.raises(gadi.GadiError):
+        gadi.solve_batched(systems, bs, [0.0], [0.5])
+    with pytest.raises(gadi.GadiError):
+        gadi.solve_batched(systems, bs, [0.5], [2.0])
+
+
+# ------------------------------------------------------------------ MLP
+def _rand_problem(seed, B):
+    rng = np.random.default_rng(seed)
+    th = omlp.init(seed).astype(np.float32)
+    th[512:576] = rng.normal(size=64).astype(np.float32) * 0.1
+    X = rng.normal(size=(B, 8)).astype(np.float32)
+    Y = rng.normal(size=(B, 2)).astype(np.float32)
+    return th, X, Y
+
+
+@pytest.mark.parametrize("B", [1, 7, 300])
+def test_mlp_forward_matches_oracle(B):
+    th, X, Y = _rand_problem(1, B)
+    p = gadi.Predictor(seed=3)
+    p.set_weights(th)
+    p.set_norm(np.zeros(8), np.ones(8))
+    y = p.forward(X)
+    yref, _ = omlp.forward(th.astype(np.float64), X.astype(np.float64))
+    assert np.allclose(y, yref, rtol=1e-5, atol=1e-5 * np.abs(yref).max())
+
+
+@pytest.mark.parametrize("B", [1, 16, 256])
+def test_mlp_gradient_matches_oracle(B):
+    th, X, Y = _rand_problem(2, B)
+    p = gadi.Predictor()
+    p.set_weights(th)
+    L, g = p.loss_grad(X, Y)
+    Lr, gr = omlp.loss_grad(th.astype(np.float64), X.astype(np.float64), Y.astype(np.float64))
+    assert abs(L - Lr) <= 1e-5 * abs(Lr)
+    assert np.linalg.norm(g - gr) <= 1e-4 * np.linalg.norm(gr)
+    big = np.abs(gr) > 1e-3 * np.abs(gr).max()
+    assert np.allclose(g[big], gr[big], rtol=1e-3)
+
+
+def test_mlp_training_follows_oracle_adam():
+    """A few full-batch Adam steps on the device track the float64 oracle's trajectory."""
+    th, X, Y = _rand_problem(4, 64)
+    p = gadi.Predictor()
+    p.set_weights(th)
+    losses = p.train(X, Y, epochs=5, lr=1e-3)
+    mu, sd = omlp.standardise_fit(X.astype(np.float64))
+    Xs = (X - mu) / sd
+    t = th.astype(np.float64)
+    m = np.zeros_like(t)
+    v = np.zeros_like(t)
+    ref = []
+    for k in range(1, 6):
+        L, g = omlp.loss_grad(t, Xs, Y.astype(np.float64))
+        ref.append(L)
+        t, m, v = omlp.adam_step(t, g, m, v, k, lr=1e-3)
+    assert np.allclose(losses, ref, rtol=1e-4)
+    assert np.allclose(p.weights(), t, rtol=1e-3, atol=1e-5)
+
+
+def test_mlp_training_fits_and_predicts_in_range():
+    rng = np.random.default_rng(5)
+    X = rng.normal(size=(200, 8)).astype(np.float32) * 3 + 1
+    Y = np.stack([np.tanh(X[:, 0] / 3) - 1.0, 0.5 + 0.2 * np.tanh(X[:, 1] / 3)], axis=1).astype(np.float32)
+    p = gadi.Predictor(seed=1)
+    losses = p.train(X, Y, epochs=1500, lr=3e-3)
+    assert losses[-1] < 0.02 * losses[0]
+    a, w = p.predict(X[0])
+    assert 1e-3 <= a <= 10.0 and 0.0 <= w <= 1.99
+    assert abs(np.log10(a) - Y[0, 0]) < 0.15 and abs(w - Y[0, 1]) < 0.1
