@@ -75,6 +75,12 @@ typedef struct {
   int32_t maxit_inner;  /* per inner solve                                      */
   int32_t on_device;    /* 1: b and x are device pointers; 0: host pointers     */
   int32_t record_history; /* 1: keep RES per sweep, read with gadi_get_history  */
+  int32_t prune_dominated; /* batched only: a trial stops with EMAXIT once its work
+                              (operator products: CG steps + 2 CGNE steps + 3 per
+                              sweep) exceeds that of a converged trial of the same
+                              system; the best trial of every system is unaffected */
+  int32_t grid_per_system; /* batched only: alpha/omega hold nsys * ntrial values,
+                              system-major (a separate trial grid per system) */
 } gadi_options;
 
 typedef struct {
@@ -93,8 +99,8 @@ typedef struct {
 typedef struct gadi_handle gadi_handle;
 typedef struct gadi_mlp gadi_mlp;
 
-/* Fill `o` with defaults: FP16_IR, eps_inner 1e-3 (fp16/fp32) , maxit_outer 20000,
- * maxit_inner 2000, host pointers, no history. */
+/* Fill `o` with defaults for `prec`: eps_inner 1e-6 (FP64) or 1e-3 (FP16/FP32),
+ * maxit_outer 20000, maxit_inner 2000, host pointers, no history, no pruning. */
 void gadi_default_options(gadi_options* o, gadi_precision prec);
 
 /* Validate A, form H and S (Section 4.1 splitting) on the union pattern of A and
@@ -122,7 +128,7 @@ int32_t gadi_get_history(gadi_handle* h, double* out, int32_t cap);
  * hs[nsys]: handles set up beforehand; b[s], x[s]: per-system host vectors
  * (x[s] receives the last iterate of trial 0 of system s and may be NULL);
  * alpha[t], omega[t] for t < ntrial (ntrial <= 16): the same trial grid for
- * every system.  info[s * ntrial + t] receives each trial's record.  Trials
+ * every system, or alpha[s * ntrial + t] with opts->grid_per_system.  info[s * ntrial + t] receives each trial's record.  Trials
  * start from x_0 = 0.  The parameter sweep of the paper's training-set
  * generation (Section 3.3.2) uses this call. */
 gadi_status gadi_ir_solve_batched(gadi_handle* const* hs, int32_t nsys, const double* const* b,
@@ -165,6 +171,8 @@ gadi_status gadi_mlp_set_weights(gadi_mlp* m, const float* w);
 gadi_status gadi_mlp_get_weights(gadi_mlp* m, float* w);
 /* feature standardisation: x_std = (x - mu) / sd, mu/sd [8] host */
 gadi_status gadi_mlp_set_norm(gadi_mlp* m, const float* mu, const float* sd);
+/* Read the standardisation in use (mu, sd [8] host out). */
+gadi_status gadi_mlp_get_norm(gadi_mlp* m, float* mu, float* sd);
 /* Forward pass on the device: X [B,8] host (raw features), Y [B,2] host out. */
 gadi_status gadi_mlp_forward(gadi_mlp* m, const float* X, int32_t B, float* Y);
 /* Loss (MSE over B*2 outputs) and gradient [4866] for standardised inputs

@@ -35,7 +35,8 @@ class _Csr(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("eps_inner", ctypes.c_double), ("maxit_outer", ctypes.c_int32),
                 ("maxit_inner", ctypes.c_int32), ("on_device", ctypes.c_int32),
-                ("record_history", ctypes.c_int32)]
+                ("record_history", ctypes.c_int32), ("prune_dominated", ctypes.c_int32),
+                ("grid_per_system", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -68,6 +69,7 @@ def _load():
         "gadi_mlp_set_weights": (i32, [vp, vp]),
         "gadi_mlp_get_weights": (i32, [vp, vp]),
         "gadi_mlp_set_norm": (i32, [vp, vp, vp]),
+        "gadi_mlp_get_norm": (i32, [vp, vp, vp]),
         "gadi_mlp_forward": (i32, [vp, vp, i32, vp]),
         "gadi_mlp_loss_grad": (i32, [vp, vp, vp, i32, vp, vp]),
         "gadi_train_mlp": (i32, [vp, vp, vp, i32, i32, ctypes.c_float, vp]),
@@ -226,21 +228,26 @@ class System:
 
 
 def solve_batched(systems, bs, alphas, omegas, tol=1e-10, prec="fp16", eps_inner=None, maxit_outer=5000,
-                  maxit_inner=2000, want_x=False):
+                  maxit_inner=2000, want_x=False, prune=False):
     """Batched (alpha, omega) sweep over many systems in one persistent launch.
 
     systems: list of System; bs: list of numpy float64 right-hand sides;
-    alphas, omegas: the trial grid (same for every system, <= 16 trials).
+    alphas, omegas: the trial grid, either one list for every system (<= 16
+    trials) or one list per system (nested, same length).
     Returns (records [nsys][ntrial] dicts, xs or None)."""
-    nsys, nt = len(systems), len(alphas)
+    per_sys = np.ndim(alphas) == 2
+    nsys = len(systems)
+    nt = len(alphas[0]) if per_sys else len(alphas)
     hs = (ctypes.c_void_p * nsys)(*[s.handle.value for s in systems])
     bsa = [np.ascontiguousarray(b, dtype=np.float64) for b in bs]
     bp = (ctypes.c_void_p * nsys)(*[b.ctypes.data for b in bsa])
     xs = [np.zeros(s.n) for s in systems] if want_x else None
     xp = (ctypes.c_void_p * nsys)(*([x.ctypes.data for x in xs] if want_x else [None] * nsys))
-    al = np.ascontiguousarray(alphas, dtype=np.float64)
-    om = np.ascontiguousarray(omegas, dtype=np.float64)
+    al = np.ascontiguousarray(np.asarray(alphas, dtype=np.float64).ravel())
+    om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64).ravel())
     o = options(prec, eps_inner, maxit_outer, maxit_inner, False, False)
+    o.prune_dominated = 1 if prune else 0
+    o.grid_per_system = 1 if per_sys else 0
     infos = (SolveInfo * (nsys * nt))()
     st = _lib.gadi_ir_solve_batched(hs, nsys, bp, xp, al.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                     om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nt, float(tol),
@@ -282,6 +289,14 @@ class Predictor:
         sd = np.ascontiguousarray(sd, dtype=np.float32)
         _check(_lib.gadi_mlp_set_norm(self._h, ctypes.c_void_p(mu.ctypes.data), ctypes.c_void_p(sd.ctypes.data)),
                "set_norm")
+
+    def norm(self):
+        """(mu, sd) feature standardisation in use."""
+        mu = np.zeros(8, np.float32)
+        sd = np.zeros(8, np.float32)
+        _check(_lib.gadi_mlp_get_norm(self._h, ctypes.c_void_p(mu.ctypes.data), ctypes.c_void_p(sd.ctypes.data)),
+               "get_norm")
+        return mu, sd
 
     def forward(self, X):
         X = np.ascontiguousarray(X, dtype=np.float32)

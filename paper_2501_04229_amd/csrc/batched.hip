@@ -40,7 +40,8 @@ struct BatchSys {
 struct BatchArgs {
   const BatchSys* sys;
   const int* order;   // unit ids, largest systems first
-  int nunits, ntrial;
+  int nunits, ntrial, nsys;
+  int grid_per_system;
   const double* alpha;
   const double* omega;
   double tol, eps;
@@ -50,6 +51,7 @@ struct BatchArgs {
   int* queue;
   DevInfo* info;      // [nunits], indexed by unit id
   double* xout;
+  unsigned long long* best_work;  // [nsys] or null: prune dominated trials
 };
 
 static __host__ __device__ inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -91,12 +93,14 @@ __global__ void __launch_bounds__(BLOCK) batched_kernel(BatchArgs ba) {
     a.vp = ws + 5 * vb;
     a.vq = ws + 6 * vb;
     a.vt = ws + 7 * vb;
-    a.alpha = ba.alpha[ti];
-    a.omega = ba.omega[ti];
+    const int gi = ba.grid_per_system ? u : ti;
+    a.alpha = ba.alpha[gi];
+    a.omega = ba.omega[gi];
     a.tol = ba.tol;
     a.eps_h = ba.eps;
     a.eps_s = ba.eps;
     a.hist = nullptr;
+    a.prune = ba.best_work ? ba.best_work + si : nullptr;
     for (int i = threadIdx.x; i < S.npad; i += BLOCK) a.x[i] = 0.0;
     __syncthreads();
     const long long t_start = wall_clock64();
@@ -114,8 +118,12 @@ __global__ void __launch_bounds__(BLOCK) batched_kernel(BatchArgs ba) {
   }
 }
 
-__global__ void zero_int_kernel(int* p) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+// Queue and pruning bounds start fresh in every launch (a kernel, not a memset,
+// so the launch can be captured in a graph).
+__global__ void reset_batch_kernel(int* queue, unsigned long long* best, int nsys) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0;
+  if (best)
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nsys; i += gridDim.x * blockDim.x) best[i] = ~0ull;
 }
 
 template <class Mode, int BLOCK>
@@ -152,7 +160,7 @@ static gadi_status batched_blocks(int prec, int block, int cap, int cus, int* G)
 
 template <class Mode, int BLOCK>
 static gadi_status launch_batched_t(const BatchArgs& ba, int G, hipStream_t stream) {
-  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, stream, ba.queue);
+  hipLaunchKernelGGL(reset_batch_kernel, dim3(1), dim3(256), 0, stream, ba.queue, ba.best_work, ba.nsys);
   hipLaunchKernelGGL((batched_kernel<Mode, BLOCK>), dim3((unsigned)G), dim3(BLOCK), 0, stream, ba);
   GADI_HIP_CHECK(hipGetLastError());
   return GADI_OK;
@@ -217,11 +225,12 @@ extern "C" gadi_status gadi_ir_solve_batched(gadi_handle* const* hs, int32_t nsy
                                              gadi_solve_info* info) {
   if (!hs || !b || !alpha || !omega || !info || nsys < 1 || ntrial < 1 || ntrial > 16 || !(tol >= 0.0))
     return GADI_EINVAL;
-  for (int t = 0; t < ntrial; ++t)
-    if (!(alpha[t] > 0.0) || !std::isfinite(alpha[t]) || !(omega[t] >= 0.0 && omega[t] < 2.0)) return GADI_EINVAL;
   gadi_options o;
   if (opts) o = *opts;
   else gadi_default_options(&o, GADI_PREC_FP16_IR);
+  const int ngrid = o.grid_per_system ? nsys * ntrial : ntrial;
+  for (int t = 0; t < ngrid; ++t)
+    if (!(alpha[t] > 0.0) || !std::isfinite(alpha[t]) || !(omega[t] >= 0.0 && omega[t] < 2.0)) return GADI_EINVAL;
   if (o.prec < GADI_PREC_FP64 || o.prec > GADI_PREC_FP32_IR || !(o.eps_inner > 0.0) || o.eps_inner >= 1.0 ||
       o.maxit_outer < 0 || o.maxit_inner < 1 || o.on_device)
     return GADI_EINVAL;
@@ -294,11 +303,12 @@ extern "C" gadi_status gadi_ir_solve_batched(gadi_handle* const* hs, int32_t nsy
   double *db = nullptr, *dal = nullptr, *dom = nullptr, *dx = nullptr;
   BatchSys* dsys = nullptr;
   int *dorder = nullptr, *dq = nullptr;
+  unsigned long long* dbest = nullptr;
   DevInfo* dinfo = nullptr;
   char* dws = nullptr;
   gadi_status st = GADI_OK;
   auto cleanup = [&]() {
-    void* ps[] = {db, dal, dom, dx, dsys, dorder, dq, dinfo, dws};
+    void* ps[] = {db, dal, dom, dx, dsys, dorder, dq, dinfo, dws, dbest};
     for (void* p : ps)
       if (p) (void)hipFree(p);
   };
@@ -321,11 +331,12 @@ extern "C" gadi_status gadi_ir_solve_batched(gadi_handle* const* hs, int32_t nsy
   BCHECK(hipMemcpy(dsys, hsys.data(), sizeof(BatchSys) * nsys, hipMemcpyHostToDevice));
   BCHECK(hipMalloc((void**)&dorder, sizeof(int) * nunits));
   BCHECK(hipMemcpy(dorder, order.data(), sizeof(int) * nunits, hipMemcpyHostToDevice));
-  BCHECK(hipMalloc((void**)&dal, sizeof(double) * ntrial));
-  BCHECK(hipMalloc((void**)&dom, sizeof(double) * ntrial));
-  BCHECK(hipMemcpy(dal, alpha, sizeof(double) * ntrial, hipMemcpyHostToDevice));
-  BCHECK(hipMemcpy(dom, omega, sizeof(double) * ntrial, hipMemcpyHostToDevice));
+  BCHECK(hipMalloc((void**)&dal, sizeof(double) * ngrid));
+  BCHECK(hipMalloc((void**)&dom, sizeof(double) * ngrid));
+  BCHECK(hipMemcpy(dal, alpha, sizeof(double) * ngrid, hipMemcpyHostToDevice));
+  BCHECK(hipMemcpy(dom, omega, sizeof(double) * ngrid, hipMemcpyHostToDevice));
   BCHECK(hipMalloc((void**)&dq, sizeof(int)));
+  if (o.prune_dominated) BCHECK(hipMalloc((void**)&dbest, sizeof(unsigned long long) * nsys));
   BCHECK(hipMalloc((void**)&dinfo, sizeof(DevInfo) * nunits));
   BCHECK(hipMemset(dinfo, 0, sizeof(DevInfo) * nunits));
   BCHECK(hipMalloc((void**)&dx, sizeof(double) * (xtotal ? xtotal : 1)));
@@ -336,6 +347,8 @@ extern "C" gadi_status gadi_ir_solve_batched(gadi_handle* const* hs, int32_t nsy
   ba.order = dorder;
   ba.nunits = nunits;
   ba.ntrial = ntrial;
+  ba.nsys = nsys;
+  ba.grid_per_system = o.grid_per_system ? 1 : 0;
   ba.alpha = dal;
   ba.omega = dom;
   ba.tol = tol;
@@ -347,6 +360,7 @@ extern "C" gadi_status gadi_ir_solve_batched(gadi_handle* const* hs, int32_t nsy
   ba.queue = dq;
   ba.info = dinfo;
   ba.xout = dx;
+  ba.best_work = dbest;
 
   // threads per block: env override, cached choice, or a timed one-sweep trial
   int lg = 0;
@@ -427,8 +441,8 @@ extern "C" gadi_status gadi_ir_solve_batched(gadi_handle* const* hs, int32_t nsy
     out.inner_S = r.inner_s;
     out.relres = r.relres;
     out.seconds = (double)r.barrier_ticks / ((rate > 0 ? rate : 100000) * 1000.0);
-    out.alpha = alpha[u % ntrial];
-    out.omega = omega[u % ntrial];
+    out.alpha = alpha[o.grid_per_system ? u : u % ntrial];
+    out.omega = omega[o.grid_per_system ? u : u % ntrial];
     out.fell_back = 0;
     out.barriers = r.barriers;
     out.barrier_seconds = total_ms * 1e-3;  // whole batch: device time of the graph launch

@@ -327,6 +327,15 @@ extern "C" gadi_status gadi_mlp_set_norm(gadi_mlp* m, const float* mu, const flo
   return GADI_OK;
 }
 
+extern "C" gadi_status gadi_mlp_get_norm(gadi_mlp* m, float* mu, float* sd) {
+  if (!m || !mu || !sd) return GADI_EINVAL;
+  for (int i = 0; i < kIn; ++i) {
+    mu[i] = m->hnorm[i];
+    sd[i] = m->hnorm[kIn + i];
+  }
+  return GADI_OK;
+}
+
 extern "C" gadi_status gadi_mlp_forward(gadi_mlp* m, const float* X, int32_t B, float* Y) {
   if (!m || !X || !Y || B < 1) return GADI_EINVAL;
   gadi_status st = ensure_buf(m->buf, B);

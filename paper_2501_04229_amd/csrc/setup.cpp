@@ -286,6 +286,8 @@ extern "C" void gadi_default_options(gadi_options* o, gadi_precision prec) {
   o->maxit_inner = 2000;
   o->on_device = 0;
   o->record_history = 0;
+  o->prune_dominated = 0;
+  o->grid_per_system = 0;
 }
 
 extern "C" gadi_status gadi_get_split_fp16(gadi_handle* h, int32_t which, int32_t* out_rp, int32_t* out_col,

@@ -52,6 +52,9 @@ struct SolveArgs {
   DevInfo* info;
   double* hist;
   long long timeout;
+  // Batched sweeps only: best work (operator products) of a converged trial
+  // of this system so far; a trial stops (EMAXIT) once its own work exceeds it.
+  unsigned long long* prune;
 };
 
 // Reduction into out[4] under the caller's synchronisation policy; leaves the
@@ -75,6 +78,9 @@ struct GridRed {
   __device__ __forceinline__ Red4 reduce(double s0, double s1, double s2, double m3, bool& ok) {
     return grid_allreduce<BLOCK>(g, s0, s1, s2, m3, ok);
   }
+  // pruning needs one value seen identically by every block; not offered here
+  __device__ __forceinline__ unsigned long long broadcast_load(const unsigned long long*) { return ~0ull; }
+  __device__ __forceinline__ void publish_min(unsigned long long*, unsigned long long) {}
 };
 
 // Synchronisation policy of the batched sweep: one block owns a whole system,
@@ -108,6 +114,18 @@ struct BlockRed {
     ++barriers;
     ok = true;
     return r;
+  }
+  // thread 0 reads, the block agrees on the value
+  __device__ __forceinline__ unsigned long long broadcast_load(const unsigned long long* p) {
+    __shared__ unsigned long long v;
+    if (threadIdx.x == 0) v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const unsigned long long r = v;
+    __syncthreads();
+    return r;
+  }
+  __device__ __forceinline__ void publish_min(unsigned long long* p, unsigned long long v) {
+    if (threadIdx.x == 0) atomicMin(p, v);
   }
 };
 
@@ -183,6 +201,13 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
     if (sweep >= a.maxit_out) {
       status = GADI_EMAXIT;
       break;
+    }
+    if (a.prune) {
+      const unsigned long long wk = (unsigned long long)(ih + 2 * is + 3 * (long long)sweep);
+      if (wk > red.broadcast_load(a.prune)) {
+        status = GADI_EMAXIT;
+        break;
+      }
     }
 
     // ---------------------------------------------------------- a3: CG on alpha I + H
@@ -349,6 +374,8 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
     ++sweep;
   }
 
+  if (a.prune && status == GADI_OK)
+    red.publish_min(a.prune, (unsigned long long)(ih + 2 * is + 3 * (long long)sweep));
   res_out.status = status;
   res_out.sweeps = sweep;
   res_out.inner_h = ih;
