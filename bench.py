@@ -48,18 +48,12 @@ def solve_bytes(prec: str, n: int, z: int, zs: int, sweeps: int, inner_h: int, i
     return float((sweeps + 1) * res + sweeps * upd + inner_h * cg + inner_s * cgne)
 
 
-def choose_params(g, A, use_mlp: bool):
-    """(alpha, omega) from the trained predictor if its weights exist, else the default (0.5, 0.5)."""
-    if use_mlp and os.path.exists(WEIGHTS):
-        import paper_2501_04229_amd as gadi
-        d = np.load(WEIGHTS)
-        p = gadi.Predictor()
-        p.set_weights(d["weights"])
-        p.set_norm(d["mu"], d["sd"])
-        f = g.features(A.dim, A.grid, A.beta)
-        a, w = p.predict(f)
-        return a, w, "mlp"
-    return 0.5, 0.5, "default"
+def load_predictor():
+    """The trained (alpha, omega) predictor, or None if no weights are present."""
+    if not os.path.exists(WEIGHTS):
+        return None
+    from paper_2501_04229_amd import predictor as pr
+    return pr.load(WEIGHTS)
 
 
 def cpu_baseline(A, b, alpha, omega, sweeps_needed, eps, budget_s=20.0):
@@ -154,27 +148,39 @@ def main():
     zs = A.nnz - A.n
     n = A.n
     bd = torch.from_numpy(b).cuda()
-    alpha, omega, psrc = choose_params(g, A, args.params == "mlp")
     eps = args.eps_inner
+    pred = load_predictor() if args.params == "mlp" else None
+    from paper_2501_04229_amd import predictor as pr
+    alpha, omega, psrc = 0.5, 0.5, "default"
+    if pred is not None:
+        alpha, omega = pr.predict(pred, g, A)
+        psrc = "mlp"
 
     def run(prec, al, om, e):
+        """One step: with the predictor, solve_auto (prediction judged by the default);
+        without, a plain solve.  Returns (x, info, launches, used)."""
+        if pred is not None and prec == args.prec:
+            x, info, used = pr.solve_auto(g, A, bd, pred, tol=1e-10, prec=prec, eps_inner=e)
+            return x, info, info["launches"], used
         x, info = g.solve(bd, al, om, tol=1e-10, prec=prec, eps_inner=e)
-        return x, info
+        return x, info, 1, "fixed"
 
     print(f"# workload {args.workload}: N={n} nnz={z} setup {setup_s:.1f}s params {psrc} "
           f"alpha={alpha:.4g} omega={omega:.4g}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        x, info = run(args.prec, alpha, omega, eps)
-        print(f"# warmup: {info['status_str']} sweeps={info['outer_sweeps']} inner_H={info['inner_H']} "
+        x, info, nl, used = run(args.prec, alpha, omega, eps)
+        print(f"# warmup: {info['status_str']} used={used} sweeps={info['outer_sweeps']} inner_H={info['inner_H']} "
               f"inner_S={info['inner_S']} {info['seconds']:.3f}s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     kernel_s = []
     infos = []
+    launches = 0
     for _ in range(args.steps):
-        x, info = run(args.prec, alpha, omega, eps)
+        x, info, nl, used = run(args.prec, alpha, omega, eps)
         kernel_s.append(info["seconds"])
         infos.append(info)
+        launches += nl
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     step_s = (t1 - t0) / args.steps
@@ -184,20 +190,38 @@ def main():
     xh = x.cpu().numpy()
     rel_err_xstar = float(np.linalg.norm(xh - xs) / np.linalg.norm(xs))
     kern = float(np.mean(kernel_s))
-    nbytes = solve_bytes(args.prec, n, z, zs, info["outer_sweeps"], info["inner_H"], info["inner_S"])
-    achieved = nbytes / kern / 1e9
+    # every solve-kernel launch of the timed region: total algorithmic bytes / total device time
+    tot_bytes = 0.0
+    for inf in infos:
+        tot_bytes += solve_bytes(args.prec, n, z, zs, inf["outer_sweeps"], inf["inner_H"], inf["inner_S"])
+    tot_bytes += (launches - len(infos)) * (12.0 * z + 22.0 * n)  # one extra residual per extra launch
+    nbytes = tot_bytes / launches
+    achieved = tot_bytes / float(np.sum(kernel_s)) / 1e9
     print(f"# fp16-IR: {step_s:.3f}s/solve, kernel {kern:.3f}s, {achieved:.0f} GB/s algorithmic, "
           f"sweeps={info['outer_sweeps']} inner_H={info['inner_H']} inner_S={info['inner_S']} "
           f"relres={info['relres']:.3e} err_vs_x*={rel_err_xstar:.3e} barriers={info['barriers']} "
           f"block0 in barriers {info['barrier_seconds']:.3f}s", file=sys.stderr, flush=True)
 
+    # the same precision with the default parameters, no predictor (reference)
+    xdf, idf = g.solve(bd, 0.5, 0.5, tol=1e-10, prec=args.prec, eps_inner=eps)
+    torch.cuda.synchronize()
+    fp16_default = {"seconds": idf["seconds"], "status": idf["status_str"], "sweeps": idf["outer_sweeps"],
+                    "inner_H": idf["inner_H"], "inner_S": idf["inner_S"], "relres": idf["relres"]}
+    print(f"# {args.prec} default (0.5, 0.5): {idf['seconds']:.3f}s sweeps={idf['outer_sweeps']}",
+          file=sys.stderr, flush=True)
+
     fp64 = None
     if not args.no_fp64:
-        x64, i64 = run("fp64", 0.5, 0.5, 1e-6)
+        run("fp64", 0.5, 0.5, 1e-6)  # first call tunes the FP64 launch shape
         torch.cuda.synchronize()
+        tf0 = time.perf_counter()
+        x64, i64, _, _ = run("fp64", 0.5, 0.5, 1e-6)
+        torch.cuda.synchronize()
+        wall64 = time.perf_counter() - tf0
         x64h = x64.cpu().numpy()
         nb64 = solve_bytes("fp64", n, z, zs, i64["outer_sweeps"], i64["inner_H"], i64["inner_S"])
-        fp64 = {"seconds": i64["seconds"], "status": i64["status_str"], "sweeps": i64["outer_sweeps"],
+        fp64 = {"seconds": i64["seconds"], "wall_seconds": wall64, "status": i64["status_str"],
+                "sweeps": i64["outer_sweeps"],
                 "inner_H": i64["inner_H"], "inner_S": i64["inner_S"], "relres": i64["relres"],
                 "rel_err_vs_xstar": float(np.linalg.norm(x64h - xs) / np.linalg.norm(xs)),
                 "algorithmic_GBs": nb64 / i64["seconds"] / 1e9,
@@ -230,18 +254,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "N": n, "nnz": z, "tol": 1e-10,
                    "eps_inner": eps if eps is not None else (1e-6 if args.prec == "fp64" else 1e-3),
-                   "alpha": alpha, "omega": omega, "params": psrc, "prec": args.prec,
+                   "alpha_predicted": alpha, "omega_predicted": omega, "params": psrc, "used": used,
+                   "prec": args.prec,
                    "solve_launch_blocks_threads": list(g.solver_blocks())},
         "solve": {"status": info["status_str"], "sweeps": info["outer_sweeps"], "inner_H": info["inner_H"],
                   "inner_S": info["inner_S"], "relres": info["relres"], "rel_err_vs_xstar": rel_err_xstar,
                   "kernel_seconds": kern, "barriers": info["barriers"],
                   "barrier_seconds_block0": info["barrier_seconds"]},
+        "default_params_same_prec": fp16_default,
         "fp64_gadi": fp64,
-        "speedup_vs_fp64_gadi": (fp64["seconds"] / kern) if fp64 else None,
+        "speedup_vs_fp64_gadi": (fp64["wall_seconds"] / step_s) if fp64 else None,
         "spmv": sp,
         "roofline": {"bound": "hbm", "kernel": f"solve_kernel<{args.prec}>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "algorithmic_bytes_per_launch": nbytes, "launch_seconds": kern, "traffic": None},
+                     "algorithmic_bytes_per_launch": nbytes, "launches": launches,
+                     "launch_seconds_mean": float(np.sum(kernel_s)) / launches, "traffic": None},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

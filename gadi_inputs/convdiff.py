@@ -177,9 +177,9 @@ def batched_family(count: int = 64, seed: int = 2, nmin: int = 128, nmax: int = 
 def train_family(count: int = 256, seeds: Sequence[int] = (10, 11, 12, 13)):
     """Small training systems for the (alpha, omega) predictor.
 
-    Three in four are 3-D (n ~ U{16..64}), one in four 2-D (n ~ U{32..160});
+    Three in four are 3-D (n ~ U{16..96}), one in four 2-D (n ~ U{32..160});
     beta ~ logU(1, 500) drawn per axis.  Systems of the same structure as the
-    large ones but 3 to 1800 times smaller, as the paper's training-set
+    large ones but up to 1800 times smaller, as the paper's training-set
     generation prescribes.  One generator per seed draws n, then beta.
     """
     out = []
@@ -188,7 +188,7 @@ def train_family(count: int = 256, seeds: Sequence[int] = (10, 11, 12, 13)):
         rng = np.random.default_rng(s)
         for i in range(per):
             dim = 2 if (i % 4 == 0) else 3
-            n = int(rng.integers(32, 161)) if dim == 2 else int(rng.integers(16, 65))
+            n = int(rng.integers(32, 161)) if dim == 2 else int(rng.integers(16, 97))
             beta = tuple(float(10.0 ** rng.uniform(0.0, math.log10(500.0))) for _ in range(dim))
             out.append((n, dim, beta))
     return out

@@ -154,9 +154,10 @@ gadi_status gadi_get_split_fp16(gadi_handle* h, int32_t which, int32_t* out_rp, 
                                 uint16_t* out_val, int64_t* nnz_out);
 
 /* Predictor features (computed on the device from the packed splitting):
- * out[8] = [ln n, dim, log10 mean(beta), max(beta) h/2 with h = 1/(grid+1),
- *           min_i(H_ii - R_i^H), max_i(H_ii + R_i^H), max_i R_i^S, min_i R_i^S],
- * R_i the off-diagonal absolute row sums.  dim, grid and beta[dim] describe the
+ * out[8] = [ln n, dim, log10 mean(beta), log10(max(beta) h/2) with h = 1/(grid+1)
+ *           (the cell Peclet number), min_i(H_ii - R_i^H), max_i(H_ii + R_i^H),
+ *           log10 max_i R_i^S, log10 min_i R_i^S],
+ * R_i the off-diagonal absolute row sums; log10 arguments floored at 1e-12.  dim, grid and beta[dim] describe the
  * convection-diffusion problem (Section 4.1) and are caller-supplied. */
 gadi_status gadi_features(gadi_handle* h, int32_t dim, int32_t grid, const double* beta, float* out);
 

@@ -168,13 +168,17 @@ class OracleSystem:
 def features(A, gersh=None) -> np.ndarray:
     """Predictor features of a convection-diffusion system.
 
-    [ln N, dim, log10 mean(beta), Pe = max_a beta_a h / 2,
-     min_i(H_ii - R_i^H), max_i(H_ii + R_i^H), max_i R_i^S, min_i R_i^S]
-    with h = 1/(n+1) and R_i the off-diagonal absolute row sums of H, S.
+    [ln N, dim, log10 mean(beta), log10 Pe with Pe = max_a beta_a h / 2,
+     min_i(H_ii - R_i^H), max_i(H_ii + R_i^H), log10 max_i R_i^S, log10 min_i R_i^S]
+    with h = 1/(n+1), R_i the off-diagonal absolute row sums of H, S, and the
+    log10 arguments floored at 1e-12.
     """
     if gersh is None:
         gersh = OracleSystem(A).gershgorin()
     beta = np.asarray(A.beta, dtype=np.float64)
     h = 1.0 / (A.grid + 1)
+
+    def lg(v):
+        return math.log10(max(v, 1e-12))
     return np.array([math.log(A.n), float(A.dim), math.log10(float(beta.mean())),
-                     float(beta.max()) * h / 2.0, gersh[0], gersh[1], gersh[2], gersh[3]])
+                     lg(float(beta.max()) * h / 2.0), gersh[0], gersh[1], lg(gersh[2]), lg(gersh[3])])

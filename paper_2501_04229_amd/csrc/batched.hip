@@ -89,10 +89,7 @@ __global__ void __launch_bounds__(BLOCK) batched_kernel(BatchArgs ba) {
     a.r = ws + vb;
     a.z = ws + 2 * vb;
     a.w = ws + 3 * vb;
-    a.vr = ws + 4 * vb;
-    a.vp = ws + 5 * vb;
-    a.vq = ws + 6 * vb;
-    a.vt = ws + 7 * vb;
+    for (int v = 0; v < 8; ++v) a.v[v] = ws + (4 + v) * vb;
     const int gi = ba.grid_per_system ? u : ti;
     a.alpha = ba.alpha[gi];
     a.omega = ba.omega[gi];
@@ -106,7 +103,7 @@ __global__ void __launch_bounds__(BLOCK) batched_kernel(BatchArgs ba) {
     const long long t_start = wall_clock64();
     BlockRed<BLOCK> red;
     DevInfo r{};
-    (void)solve_body<Mode, BLOCK>(a, red, 0, S.npad / BLOCK, r);
+    (void)solve_body<Mode, BLOCK, false>(a, red, 0, S.npad / BLOCK, r);
     if (threadIdx.x == 0) {
       r.barriers = red.barriers;
       r.barrier_ticks = wall_clock64() - t_start;  // the unit's wall-clock ticks
@@ -290,7 +287,7 @@ extern "C" gadi_status gadi_ir_solve_batched(gadi_handle* const* hs, int32_t nsy
     for (int t = 0; t < ntrial; ++t) order.push_back(s * ntrial + t);
 
   const size_t vb = align256((size_t)max_npad * sizeof(double));
-  const size_t ws_stride = 8 * vb;
+  const size_t ws_stride = 12 * vb;
   int cus = 0, dev = 0;
   GADI_HIP_CHECK(hipGetDevice(&dev));
   GADI_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));

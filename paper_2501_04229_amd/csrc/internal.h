@@ -101,6 +101,7 @@ struct System {
   // launch shape of the solve kernel per precision mode, chosen by the autotuner
   int tuned_block[3] = {0, 0, 0};
   int tuned_per_cu[3] = {0, 0, 0};
+  int tuned_fused[3] = {0, 0, 0};
   int last_blocks = 0;
   int last_block_threads = 0;
 };

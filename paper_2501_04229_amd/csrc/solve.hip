@@ -14,14 +14,14 @@
 namespace gadi {
 
 // One large system: persistent cooperative launch, one band of rows per block.
-template <class Mode, int BLOCK>
+template <class Mode, int BLOCK, bool FUSED>
 __global__ void __launch_bounds__(BLOCK) solve_kernel(SolveArgs a) {
   GridRed<BLOCK> red{Grid{a.sync, a.flags, a.part, a.result, gridDim.x, 0ull, a.timeout, 0ll}};
   const unsigned lb = logical_block(blockIdx.x, gridDim.x);
   const int t0 = (int)((long long)a.ntiles * lb / gridDim.x);
   const int t1 = (int)((long long)a.ntiles * (lb + 1) / gridDim.x);
   DevInfo r{};
-  if (!solve_body<Mode, BLOCK>(a, red, t0, t1, r)) return;
+  if (!solve_body<Mode, BLOCK, FUSED>(a, red, t0, t1, r)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     r.barriers = (long long)red.g.epoch;
     r.barrier_ticks = red.g.wait_ticks;
@@ -80,8 +80,8 @@ int num_cus() { return g_num_cus; }
 gadi_status ensure_workspace(System& s) {
   GADI_HIP_CHECK(hipSetDevice(s.device));
   if (s.ws) return GADI_OK;
-  // b, x (double) + r, z, w (double-sized) + 4 Krylov vectors (double-sized)
-  s.ws_bytes = (size_t)s.npad * sizeof(double) * 9;
+  // b, x (double) + r, z, w (double-sized) + 8 Krylov vectors (double-sized)
+  s.ws_bytes = (size_t)s.npad * sizeof(double) * 13;
   GADI_HIP_CHECK(hipMalloc(&s.ws, s.ws_bytes));
   GADI_HIP_CHECK(hipMemset(s.ws, 0, s.ws_bytes));
   GADI_HIP_CHECK(hipMalloc((void**)&s.sync, sizeof(SyncState)));
@@ -116,10 +116,10 @@ __global__ void fill_zero_kernel(double* __restrict__ p, long long n) {
 
 gadi_status ensure_fp32_public(System& s) { return ensure_fp32(s); }
 
-template <class Mode, int BLOCK>
+template <class Mode, int BLOCK, bool FUSED>
 static gadi_status launch_t(System& s, SolveArgs a, int per_cu) {
   int nb = 0;
-  GADI_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, solve_kernel<Mode, BLOCK>, BLOCK, 0));
+  GADI_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, solve_kernel<Mode, BLOCK, FUSED>, BLOCK, 0));
   if (nb < 1 || per_cu > nb) return GADI_EINVAL;  // not co-resident: not a valid shape
   const int ntiles = s.npad / BLOCK;
   long long G = (long long)per_cu * num_cus();
@@ -130,54 +130,66 @@ static gadi_status launch_t(System& s, SolveArgs a, int per_cu) {
   hipLaunchKernelGGL(reset_sync_kernel, dim3(32), dim3(1024), 0, s.stream, s.sync, s.flags, s.info);
   GADI_HIP_CHECK(hipGetLastError());
   void* kargs[] = {(void*)&a};
-  GADI_HIP_CHECK(hipLaunchCooperativeKernel((const void*)solve_kernel<Mode, BLOCK>, dim3((unsigned)G), dim3(BLOCK),
+  GADI_HIP_CHECK(hipLaunchCooperativeKernel((const void*)solve_kernel<Mode, BLOCK, FUSED>, dim3((unsigned)G), dim3(BLOCK),
                                             kargs, 0, s.stream));
   s.last_blocks = (int)G;
   s.last_block_threads = BLOCK;
   return GADI_OK;
 }
 
-template <class Mode>
+template <class Mode, bool FUSED>
 static gadi_status launch_mode(System& s, const SolveArgs& a, int block, int per_cu) {
   switch (block) {
-    case 256: return launch_t<Mode, 256>(s, a, per_cu);
-    case 512: return launch_t<Mode, 512>(s, a, per_cu);
-    case 1024: return launch_t<Mode, 1024>(s, a, per_cu);
+    case 256: return launch_t<Mode, 256, FUSED>(s, a, per_cu);
+    case 512: return launch_t<Mode, 512, FUSED>(s, a, per_cu);
+    case 1024: return launch_t<Mode, 1024, FUSED>(s, a, per_cu);
   }
   return GADI_EINVAL;
 }
 
-static gadi_status launch_solve(System& s, int prec, const SolveArgs& a, int block, int per_cu) {
-  if (prec == GADI_PREC_FP16_IR) return launch_mode<ModeF16>(s, a, block, per_cu);
-  if (prec == GADI_PREC_FP32_IR) return launch_mode<ModeF32>(s, a, block, per_cu);
-  return launch_mode<ModeF64>(s, a, block, per_cu);
+// fused: Chronopoulos-Gear inner solves (one reduction per CG step) instead of
+// Hestenes-Stiefel (two)
+static gadi_status launch_solve(System& s, int prec, const SolveArgs& a, int block, int per_cu, bool fused) {
+  if (fused) {
+    if (prec == GADI_PREC_FP16_IR) return launch_mode<ModeF16, true>(s, a, block, per_cu);
+    if (prec == GADI_PREC_FP32_IR) return launch_mode<ModeF32, true>(s, a, block, per_cu);
+    return launch_mode<ModeF64, true>(s, a, block, per_cu);
+  }
+  if (prec == GADI_PREC_FP16_IR) return launch_mode<ModeF16, false>(s, a, block, per_cu);
+  if (prec == GADI_PREC_FP32_IR) return launch_mode<ModeF32, false>(s, a, block, per_cu);
+  return launch_mode<ModeF64, false>(s, a, block, per_cu);
 }
 
-// Autotuner: time two outer sweeps from x = 0 in every candidate launch shape
-// (threads per block x blocks per compute unit) and keep the one with the
-// lowest time per phase.  Runs once per handle and precision; the choice is
-// overridden by GADI_SOLVE_BLOCK / GADI_BLOCKS_PER_CU.
+// Autotuner: time three outer sweeps from x = 0 in every candidate (threads
+// per block x blocks per compute unit x inner-solver variant), after one
+// untimed warm-up launch, best of two passes, and keep the lowest time per
+// inner step.  Runs once per handle and precision; GADI_SOLVE_BLOCK,
+// GADI_BLOCKS_PER_CU and GADI_SOLVE_FUSED override it.
 static gadi_status tune_solve(System& s, int prec, SolveArgs a, double* dx) {
   if (s.tuned_block[prec]) return GADI_OK;
   const char* eb = std::getenv("GADI_SOLVE_BLOCK");
   const char* ec = std::getenv("GADI_BLOCKS_PER_CU");
-  if (eb || ec) {
+  const char* ef = std::getenv("GADI_SOLVE_FUSED");
+  if (eb || ec || ef) {
     s.tuned_block[prec] = eb ? std::atoi(eb) : 1024;
     s.tuned_per_cu[prec] = ec ? std::atoi(ec) : 1;
+    s.tuned_fused[prec] = ef ? (std::atoi(ef) != 0) : 0;
     return GADI_OK;
   }
-  static const int cand[][2] = {{1024, 1}, {512, 2}, {512, 1}, {256, 4}, {256, 2}};
+  // {threads per block, blocks per CU, fused inner solves}
+  static const int cand[][3] = {{1024, 1, 0}, {512, 2, 0}, {512, 1, 0}, {256, 4, 0}, {256, 2, 0},
+                                {1024, 1, 1}, {512, 2, 1}, {512, 1, 1}, {256, 4, 1}, {256, 2, 1}};
   a.maxit_out = a.maxit_out < 3 ? a.maxit_out : 3;
   a.hist = nullptr;
   a.hist_cap = 0;
   double best = 1e300;
-  int bb = 1024, bc = 1;
+  int bb = 1024, bc = 1, bf = 0;
   // the first launch also pays code loading and cold caches: run it untimed
   for (int pass = 0; pass < 3; ++pass) {
     for (const auto& c : cand) {
       hipLaunchKernelGGL(fill_zero_kernel, dim3(256), dim3(256), 0, s.stream, dx, (long long)s.npad);
       GADI_HIP_CHECK(hipEventRecord(s.ev0, s.stream));
-      gadi_status st = launch_solve(s, prec, a, c[0], c[1]);
+      gadi_status st = launch_solve(s, prec, a, c[0], c[1], c[2] != 0);
       if (st == GADI_EINVAL) continue;
       if (st != GADI_OK) return st;
       GADI_HIP_CHECK(hipEventRecord(s.ev1, s.stream));
@@ -186,20 +198,24 @@ static gadi_status tune_solve(System& s, int prec, SolveArgs a, double* dx) {
       GADI_HIP_CHECK(hipStreamSynchronize(s.stream));
       float ms = 0.f;
       GADI_HIP_CHECK(hipEventElapsedTime(&ms, s.ev0, s.ev1));
-      const double per = ms / (double)(di.barriers > 0 ? di.barriers : 1);
+      // time per inner step (CG + CGNE steps + 4 per sweep) is comparable across variants
+      const double steps = (double)(di.inner_h + di.inner_s + 4ll * di.sweeps);
+      const double per = ms / (steps > 0 ? steps : 1.0);
       if (pass == 0) break;  // warm-up launch only
       if (std::getenv("GADI_DEBUG"))
-        std::fprintf(stderr, "gadi: tune prec %d block %d x %d/CU: %.2f us/phase (%lld phases)\n", prec, c[0], c[1],
-                     per * 1e3, (long long)di.barriers);
+        std::fprintf(stderr, "gadi: tune prec %d block %d x %d/CU fused %d: %.2f us/step (%lld phases)\n", prec,
+                     c[0], c[1], c[2], per * 1e3, (long long)di.barriers);
       if (per < best) {
         best = per;
         bb = c[0];
         bc = c[1];
+        bf = c[2];
       }
     }
   }
   s.tuned_block[prec] = bb;
   s.tuned_per_cu[prec] = bc;
+  s.tuned_fused[prec] = bf;
   return GADI_OK;
 }
 
@@ -270,10 +286,7 @@ extern "C" gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x,
   a.r = vbase;
   a.z = vbase + vbytes;
   a.w = vbase + 2 * vbytes;
-  a.vr = vbase + 3 * vbytes;
-  a.vp = vbase + 4 * vbytes;
-  a.vq = vbase + 5 * vbytes;
-  a.vt = vbase + 6 * vbytes;
+  for (int v = 0; v < 8; ++v) a.v[v] = vbase + (3 + v) * vbytes;
   a.alpha = alpha;
   a.omega = omega;
   a.tol = tol;
@@ -302,7 +315,7 @@ extern "C" gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x,
   if ((st = tune_solve(s, o.prec, a, dx)) != GADI_OK) return st;
   GADI_HIP_CHECK(hipMemcpyAsync(dx, x, sizeof(double) * s.n, kin, s.stream));
   GADI_HIP_CHECK(hipEventRecord(s.ev0, s.stream));
-  st = launch_solve(s, o.prec, a, s.tuned_block[o.prec], s.tuned_per_cu[o.prec]);
+  st = launch_solve(s, o.prec, a, s.tuned_block[o.prec], s.tuned_per_cu[o.prec], s.tuned_fused[o.prec] != 0);
   if (st != GADI_OK) return st;
   GADI_HIP_CHECK(hipEventRecord(s.ev1, s.stream));
   GADI_HIP_CHECK(hipMemcpyAsync(x, dx, sizeof(double) * s.n, kout, s.stream));

@@ -40,10 +40,7 @@ struct SolveArgs {
   void* r;
   void* z;
   void* w;
-  void* vr;
-  void* vp;
-  void* vq;
-  void* vt;
+  void* v[8];  // storage-precision vectors: r (2), w (2), s (2), p, t
   double alpha, omega, tol, eps_h, eps_s;
   SyncState* sync;
   unsigned long long* flags;
@@ -133,7 +130,35 @@ static __device__ __forceinline__ int clamp_exp(int e) { return e < -120 ? -120 
 
 // The refinement loop of Algorithm 1 for rows [t0 * BLOCK, t1 * BLOCK) of one
 // system.  Returns false if a barrier timed out; otherwise fills `res`.
-template <class Mode, int BLOCK, class Red>
+//
+// Both inner solves use the Chronopoulos-Gear form of CG: with w = K r and
+// s = K p carried by recurrence, the two inner products of a step,
+// gamma = r.r and delta = r.K r, come from one reduction.  Step k updates
+//   s_k = w_k + beta_k s_{k-1},  p_k = r_k + beta_k p_{k-1},
+//   z += a_k p_k,  r_{k+1} = r_k - a_k s_k,  w_{k+1} = K r_{k+1},
+// with beta_k = gamma_k / gamma_{k-1} and a_k = gamma_k / (delta_k - beta_k gamma_k / a_{k-1}).
+// (FUSED = true.)  The other variant (FUSED = false) is Hestenes-Stiefel CG
+// with q_{k+1} = K p_{k+1} = K r_{k+1} + beta q_k folded into the product
+// phase: two phases per CG step, three per CGNE step, but no recomputation.
+// The product K r_{k+1} needs r_{k+1} at neighbouring rows, which other
+// blocks are writing in the same phase; each block recomputes those values
+// from r_k, w_k, s_{k-1} (read from the previous phase's buffers, hence
+// ping-pong buffers for r, w, s) with the same fused operations and the same
+// roundings as their owner, so every copy is bit-identical.  A CG step on
+// alpha I + H is one phase; a CGNE step on I - (S/alpha)^2 is two (the
+// second product needs the first one's result at neighbouring rows).
+template <class AT>
+__device__ __forceinline__ AT fma_at(AT a, AT b, AT c);
+template <>
+__device__ __forceinline__ float fma_at<float>(float a, float b, float c) {
+  return fmaf(a, b, c);
+}
+template <>
+__device__ __forceinline__ double fma_at<double>(double a, double b, double c) {
+  return fma(a, b, c);
+}
+
+template <class Mode, int BLOCK, bool FUSED, class Red>
 __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0, int t1, DevInfo& res_out) {
   using MT = typename Mode::MT;
   using VT = typename Mode::VT;
@@ -150,11 +175,12 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
   const MT* __restrict__ hdiag = (const MT*)a.h_diag;
   RT* __restrict__ r = (RT*)a.r;
   ST* __restrict__ z = (ST*)a.z;
-  ST* __restrict__ w = (ST*)a.w;
-  VT* __restrict__ vr = (VT*)a.vr;
-  VT* __restrict__ vp = (VT*)a.vp;
-  VT* __restrict__ vq = (VT*)a.vq;
-  VT* __restrict__ vt = (VT*)a.vt;
+  ST* __restrict__ wsol = (ST*)a.w;
+  VT* const R[2] = {(VT*)a.v[0], (VT*)a.v[1]};
+  VT* const W[2] = {(VT*)a.v[2], (VT*)a.v[3]};
+  VT* const Sv[2] = {(VT*)a.v[4], (VT*)a.v[5]};
+  VT* __restrict__ P = (VT*)a.v[6];
+  VT* __restrict__ T = (VT*)a.v[7];
   double* __restrict__ x = a.x;
   const double* __restrict__ b = a.b;
 
@@ -163,6 +189,10 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
   const AT two_m_omega = (AT)(2.0 - a.omega);
   const double eps_h2 = a.eps_h * a.eps_h;
   const double eps_s2 = a.eps_s * a.eps_s;
+  const int overflow_status = Mode::id == GADI_PREC_FP16_IR ? GADI_EOVERFLOW16 : GADI_EDIVERGED;
+
+  // value rounded to the storage type and read back
+  auto rnd = [](AT v) { return ld<AT>(st<VT>(v)); };
 
   double out[4];
   double rho0 = 0.0, res = 0.0;
@@ -215,74 +245,150 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
     (void)frexp(rmax, &e1);
     e1 = clamp_exp(e1);
     const AT sc1 = (AT)ldexp(1.0, -e1);
-    double pq, rr, rr0, zmax = 0.0;
-    {
-      double s0 = 0.0, s1 = 0.0;
-      for (int t = t0; t < t1; ++t) {
-        const int row = t * BLOCK + tid;
-        const VT pi = st<VT>((AT)r[row] * sc1);
-        const AT api = ld<AT>(pi);
-        const AT kp = (alpha + ld<AT>(hdiag[row])) * api +
-                      row_sum<AT>(row, sp, col, hoff, [&](int c) { return ld<AT>(st<VT>((AT)r[c] * sc1)); });
-        const VT qi = st<VT>(kp);
-        vr[row] = pi;
-        vp[row] = pi;
-        vq[row] = qi;
-        s0 += (double)api * (double)ld<AT>(qi);
-        s1 += (double)api * (double)api;
-      }
-      ALLREDUCE(s0, s1, 0.0, 0.0);
-      pq = out[0];
-      rr0 = out[1];
-      rr = rr0;
-    }
+    double zmax = 0.0;
     int it = 0;
-    if (rr0 > 0.0) {
-      for (;;) {
-        if (!(pq > 0.0) || !isfinite(pq)) {
-          if (it == 0) status = isfinite(pq) ? GADI_ENOTSPD : (Mode::id == GADI_PREC_FP16_IR ? GADI_EOVERFLOW16 : GADI_EDIVERGED);
-          break;
-        }
-        const AT ak = (AT)(rr / pq);
-        double s0 = 0.0, m3 = 0.0;
+    if constexpr (FUSED) {
+      {
+        // r_0 = r * 2^-e1 in storage precision, w_0 = K r_0
+        double g0 = 0.0, d0 = 0.0;
         for (int t = t0; t < t1; ++t) {
           const int row = t * BLOCK + tid;
-          const AT pi = ld<AT>(vp[row]);
-          const ST zi = (it == 0 ? ST(0) : z[row]) + (ST)(ak * pi);
-          z[row] = zi;
-          const VT ri = st<VT>(ld<AT>(vr[row]) - ak * ld<AT>(vq[row]));
-          vr[row] = ri;
-          const double dr = (double)ld<AT>(ri);
-          s0 += dr * dr;
-          m3 = fmax(m3, fabs((double)zi));
-        }
-        ALLREDUCE(s0, 0.0, 0.0, m3);
-        const double rr_new = out[0];
-        zmax = out[3];
-        ++it;
-        if (rr_new <= eps_h2 * rr0 || it >= a.maxit_in || !isfinite(rr_new)) break;
-        const AT beta = (AT)(rr_new / rr);
-        rr = rr_new;
-        s0 = 0.0;
-        for (int t = t0; t < t1; ++t) {
-          const int row = t * BLOCK + tid;
-          const AT ri = ld<AT>(vr[row]);
+          const AT ri = rnd((AT)r[row] * sc1);
           const AT kr = (alpha + ld<AT>(hdiag[row])) * ri +
-                        row_sum<AT>(row, sp, col, hoff, [&](int c) { return ld<AT>(vr[c]); });
-          const VT pn = st<VT>(ri + beta * ld<AT>(vp[row]));
-          const VT qn = st<VT>(kr + beta * ld<AT>(vq[row]));
-          vp[row] = pn;
-          vq[row] = qn;
-          s0 += (double)ld<AT>(pn) * (double)ld<AT>(qn);
+                        row_sum<AT>(row, sp, col, hoff, [&](int c) { return rnd((AT)r[c] * sc1); });
+          const AT wi = rnd(kr);
+          R[0][row] = st<VT>(ri);
+          W[0][row] = st<VT>(wi);
+          g0 += (double)ri * (double)ri;
+          d0 += (double)wi * (double)ri;
         }
-        ALLREDUCE(s0, 0.0, 0.0, 0.0);
+        ALLREDUCE(g0, d0, 0.0, 0.0);
+      }
+      double gam = out[0], del = out[1];
+      const double gam0 = gam;
+      if (gam0 > 0.0) {
+        double gam_prev = 1.0, a_prev = 1.0;
+        for (int k = 0;; ++k) {
+          const double beta = k == 0 ? 0.0 : gam / gam_prev;
+          const double den = k == 0 ? del : del - beta * gam / a_prev;
+          if (!(den > 0.0) || !isfinite(den)) {
+            if (k == 0) status = isfinite(den) ? GADI_ENOTSPD : overflow_status;
+            break;
+          }
+          const double ak = gam / den;
+          const AT akt = (AT)ak, bkt = (AT)beta;
+          const VT* __restrict__ rk = R[k & 1];
+          const VT* __restrict__ wk = W[k & 1];
+          const VT* __restrict__ sprev = Sv[(k + 1) & 1];
+          VT* __restrict__ snew = Sv[k & 1];
+          VT* __restrict__ rnew = R[(k + 1) & 1];
+          VT* __restrict__ wnew = W[(k + 1) & 1];
+          // r_{k+1} at row c, computed exactly as its owner computes it
+          auto r_next = [&](int c) {
+            const AT sc = k == 0 ? ld<AT>(wk[c]) : rnd(fma_at<AT>(bkt, ld<AT>(sprev[c]), ld<AT>(wk[c])));
+            return rnd(fma_at<AT>(-akt, sc, ld<AT>(rk[c])));
+          };
+          double g1 = 0.0, d1 = 0.0, m3 = 0.0;
+          for (int t = t0; t < t1; ++t) {
+            const int row = t * BLOCK + tid;
+            const AT ri = ld<AT>(rk[row]);
+            const AT si = k == 0 ? ld<AT>(wk[row]) : rnd(fma_at<AT>(bkt, ld<AT>(sprev[row]), ld<AT>(wk[row])));
+            const AT pi = k == 0 ? ri : rnd(fma_at<AT>(bkt, ld<AT>(P[row]), ri));
+            const ST zi = (k == 0 ? ST(0) : z[row]) + (ST)(akt * pi);
+            const AT rn = rnd(fma_at<AT>(-akt, si, ri));
+            const AT kr = (alpha + ld<AT>(hdiag[row])) * rn + row_sum<AT>(row, sp, col, hoff, r_next);
+            const AT wn = rnd(kr);
+            snew[row] = st<VT>(si);
+            P[row] = st<VT>(pi);
+            z[row] = zi;
+            rnew[row] = st<VT>(rn);
+            wnew[row] = st<VT>(wn);
+            g1 += (double)rn * (double)rn;
+            d1 += (double)wn * (double)rn;
+            m3 = fmax(m3, fabs((double)zi));
+          }
+          ALLREDUCE(g1, d1, 0.0, m3);
+          gam_prev = gam;
+          a_prev = ak;
+          gam = out[0];
+          del = out[1];
+          zmax = out[3];
+          it = k + 1;
+          if (gam <= eps_h2 * gam0 || it >= a.maxit_in || !isfinite(gam)) break;
+        }
+      }
+    } else {
+      VT* __restrict__ vr = R[0];
+      VT* __restrict__ vp = P;
+      VT* __restrict__ vq = W[0];
+      double pq, rr, rr0;
+      {
+        double s0 = 0.0, s1 = 0.0;
+        for (int t = t0; t < t1; ++t) {
+          const int row = t * BLOCK + tid;
+          const VT pi = st<VT>((AT)r[row] * sc1);
+          const AT api = ld<AT>(pi);
+          const AT kp = (alpha + ld<AT>(hdiag[row])) * api +
+                        row_sum<AT>(row, sp, col, hoff, [&](int c) { return ld<AT>(st<VT>((AT)r[c] * sc1)); });
+          const VT qi = st<VT>(kp);
+          vr[row] = pi;
+          vp[row] = pi;
+          vq[row] = qi;
+          s0 += (double)api * (double)ld<AT>(qi);
+          s1 += (double)api * (double)api;
+        }
+        ALLREDUCE(s0, s1, 0.0, 0.0);
         pq = out[0];
+        rr0 = out[1];
+        rr = rr0;
+      }
+      if (rr0 > 0.0) {
+        for (;;) {
+          if (!(pq > 0.0) || !isfinite(pq)) {
+            if (it == 0) status = isfinite(pq) ? GADI_ENOTSPD : (Mode::id == GADI_PREC_FP16_IR ? GADI_EOVERFLOW16 : GADI_EDIVERGED);
+            break;
+          }
+          const AT ak = (AT)(rr / pq);
+          double s0 = 0.0, m3 = 0.0;
+          for (int t = t0; t < t1; ++t) {
+            const int row = t * BLOCK + tid;
+            const AT pi = ld<AT>(vp[row]);
+            const ST zi = (it == 0 ? ST(0) : z[row]) + (ST)(ak * pi);
+            z[row] = zi;
+            const VT ri = st<VT>(ld<AT>(vr[row]) - ak * ld<AT>(vq[row]));
+            vr[row] = ri;
+            const double dr = (double)ld<AT>(ri);
+            s0 += dr * dr;
+            m3 = fmax(m3, fabs((double)zi));
+          }
+          ALLREDUCE(s0, 0.0, 0.0, m3);
+          const double rr_new = out[0];
+          zmax = out[3];
+          ++it;
+          if (rr_new <= eps_h2 * rr0 || it >= a.maxit_in || !isfinite(rr_new)) break;
+          const AT beta = (AT)(rr_new / rr);
+          rr = rr_new;
+          s0 = 0.0;
+          for (int t = t0; t < t1; ++t) {
+            const int row = t * BLOCK + tid;
+            const AT ri = ld<AT>(vr[row]);
+            const AT kr = (alpha + ld<AT>(hdiag[row])) * ri +
+                          row_sum<AT>(row, sp, col, hoff, [&](int c) { return ld<AT>(vr[c]); });
+            const VT pn = st<VT>(ri + beta * ld<AT>(vp[row]));
+            const VT qn = st<VT>(kr + beta * ld<AT>(vq[row]));
+            vp[row] = pn;
+            vq[row] = qn;
+            s0 += (double)ld<AT>(pn) * (double)ld<AT>(qn);
+          }
+          ALLREDUCE(s0, 0.0, 0.0, 0.0);
+          pq = out[0];
+        }
       }
     }
     ih += it;
     if (status != GADI_EMAXIT) break;  // inner breakdown on the first step
     if (!isfinite(zmax)) {
-      status = Mode::id == GADI_PREC_FP16_IR ? GADI_EOVERFLOW16 : GADI_EDIVERGED;
+      status = overflow_status;
       break;
     }
 
@@ -293,68 +399,160 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
       (void)frexp((double)two_m_omega * zmax, &e2);
       e2 = clamp_exp(e2);
       const AT sc2 = (AT)ldexp(1.0, -e2);
-      double rrs0;
-      {
-        double s1 = 0.0;
-        for (int t = t0; t < t1; ++t) {
-          const int row = t * BLOCK + tid;
-          const VT gi = st<VT>(two_m_omega * (AT)z[row] * sc2);
-          const AT tv = inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) {
-                          return ld<AT>(st<VT>(two_m_omega * (AT)z[c] * sc2));
-                        });
-          vr[row] = gi;
-          vp[row] = gi;
-          vt[row] = st<VT>(tv);
-          const double dg = (double)ld<AT>(gi);
-          s1 += dg * dg;
+      auto g_at = [&](int c) { return rnd(two_m_omega * (AT)z[c] * sc2); };
+      if constexpr (FUSED) {
+        // r_0 = g, t = (S/alpha) g
+        {
+          double g0 = 0.0;
+          for (int t = t0; t < t1; ++t) {
+            const int row = t * BLOCK + tid;
+            const AT gi = g_at(row);
+            const AT tv = inv_alpha * row_sum<AT>(row, sp, col, soff, g_at);
+            R[0][row] = st<VT>(gi);
+            T[row] = st<VT>(tv);
+            g0 += (double)gi * (double)gi;
+          }
+          ALLREDUCE(g0, 0.0, 0.0, 0.0);
         }
-        ALLREDUCE(0.0, s1, 0.0, 0.0);
-        rrs0 = out[1];
-      }
-      double rrs = rrs0;
-      if (rrs0 > 0.0) {
-        for (;;) {
-          // q = p - (S/alpha) t, with t = (S/alpha) p
-          double s0 = 0.0;
+        const double gs0 = out[0];
+        // w_0 = r_0 - (S/alpha) t
+        {
+          double d0 = 0.0;
           for (int t = t0; t < t1; ++t) {
             const int row = t * BLOCK + tid;
-            const AT pi = ld<AT>(vp[row]);
-            const AT qv = pi - inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) { return ld<AT>(vt[c]); });
-            const VT qi = st<VT>(qv);
-            vq[row] = qi;
-            s0 += (double)pi * (double)ld<AT>(qi);
+            const AT ri = ld<AT>(R[0][row]);
+            const AT wi = rnd(ri - inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) { return ld<AT>(T[c]); }));
+            W[0][row] = st<VT>(wi);
+            d0 += (double)wi * (double)ri;
           }
-          ALLREDUCE(s0, 0.0, 0.0, 0.0);
-          const double pqs = out[0];
-          if (!(pqs > 0.0) || !isfinite(pqs)) {
-            if (its == 0) status = isfinite(pqs) ? GADI_ENOTSPD : (Mode::id == GADI_PREC_FP16_IR ? GADI_EOVERFLOW16 : GADI_EDIVERGED);
-            break;
+          ALLREDUCE(0.0, d0, 0.0, 0.0);
+        }
+        double gam = gs0, del = out[1];
+        if (gs0 > 0.0) {
+          double gam_prev = 1.0, a_prev = 1.0;
+          for (int k = 0;; ++k) {
+            const double beta = k == 0 ? 0.0 : gam / gam_prev;
+            const double den = k == 0 ? del : del - beta * gam / a_prev;
+            if (!(den > 0.0) || !isfinite(den)) {
+              if (k == 0) status = isfinite(den) ? GADI_ENOTSPD : overflow_status;
+              break;
+            }
+            const double ak = gam / den;
+            const AT akt = (AT)ak, bkt = (AT)beta;
+            const VT* __restrict__ rk = R[k & 1];
+            const VT* __restrict__ wk = W[k & 1];
+            const VT* __restrict__ sprev = Sv[(k + 1) & 1];
+            VT* __restrict__ snew = Sv[k & 1];
+            VT* __restrict__ rnew = R[(k + 1) & 1];
+            VT* __restrict__ wnew = W[(k + 1) & 1];
+            auto r_next = [&](int c) {
+              const AT sc = k == 0 ? ld<AT>(wk[c]) : rnd(fma_at<AT>(bkt, ld<AT>(sprev[c]), ld<AT>(wk[c])));
+              return rnd(fma_at<AT>(-akt, sc, ld<AT>(rk[c])));
+            };
+            // step + t = (S/alpha) r_{k+1}
+            double g1 = 0.0;
+            for (int t = t0; t < t1; ++t) {
+              const int row = t * BLOCK + tid;
+              const AT ri = ld<AT>(rk[row]);
+              const AT si = k == 0 ? ld<AT>(wk[row]) : rnd(fma_at<AT>(bkt, ld<AT>(sprev[row]), ld<AT>(wk[row])));
+              const AT pi = k == 0 ? ri : rnd(fma_at<AT>(bkt, ld<AT>(P[row]), ri));
+              wsol[row] = (k == 0 ? ST(0) : wsol[row]) + (ST)(akt * pi);
+              const AT rn = rnd(fma_at<AT>(-akt, si, ri));
+              const AT tv = inv_alpha * row_sum<AT>(row, sp, col, soff, r_next);
+              snew[row] = st<VT>(si);
+              P[row] = st<VT>(pi);
+              rnew[row] = st<VT>(rn);
+              T[row] = st<VT>(tv);
+              g1 += (double)rn * (double)rn;
+            }
+            ALLREDUCE(g1, 0.0, 0.0, 0.0);
+            gam_prev = gam;
+            a_prev = ak;
+            gam = out[0];
+            its = k + 1;
+            if (gam <= eps_s2 * gs0 || its >= a.maxit_in || !isfinite(gam)) break;
+            // w_{k+1} = r_{k+1} - (S/alpha) t
+            double d1 = 0.0;
+            for (int t = t0; t < t1; ++t) {
+              const int row = t * BLOCK + tid;
+              const AT rn = ld<AT>(rnew[row]);
+              const AT wn = rnd(rn - inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) { return ld<AT>(T[c]); }));
+              wnew[row] = st<VT>(wn);
+              d1 += (double)wn * (double)rn;
+            }
+            ALLREDUCE(0.0, d1, 0.0, 0.0);
+            del = out[1];
           }
-          const AT ak = (AT)(rrs / pqs);
-          s0 = 0.0;
+        }
+      } else {
+        VT* __restrict__ vr = R[0];
+        VT* __restrict__ vp = P;
+        VT* __restrict__ vq = W[0];
+        VT* __restrict__ vt = T;
+        ST* __restrict__ w = wsol;
+        double rrs0;
+        {
+          double s1 = 0.0;
           for (int t = t0; t < t1; ++t) {
             const int row = t * BLOCK + tid;
-            const AT pi = ld<AT>(vp[row]);
-            w[row] = (its == 0 ? ST(0) : w[row]) + (ST)(ak * pi);
-            const VT ri = st<VT>(ld<AT>(vr[row]) - ak * ld<AT>(vq[row]));
-            vr[row] = ri;
-            const double dr = (double)ld<AT>(ri);
-            s0 += dr * dr;
+            const VT gi = st<VT>(two_m_omega * (AT)z[row] * sc2);
+            const AT tv = inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) {
+                            return ld<AT>(st<VT>(two_m_omega * (AT)z[c] * sc2));
+                          });
+            vr[row] = gi;
+            vp[row] = gi;
+            vt[row] = st<VT>(tv);
+            const double dg = (double)ld<AT>(gi);
+            s1 += dg * dg;
           }
-          ALLREDUCE(s0, 0.0, 0.0, 0.0);
-          const double rr_new = out[0];
-          ++its;
-          if (rr_new <= eps_s2 * rrs0 || its >= a.maxit_in || !isfinite(rr_new)) break;
-          const AT beta = (AT)(rr_new / rrs);
-          rrs = rr_new;
-          for (int t = t0; t < t1; ++t) {
-            const int row = t * BLOCK + tid;
-            const AT ri = ld<AT>(vr[row]);
-            const AT sr = inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) { return ld<AT>(vr[c]); });
-            vt[row] = st<VT>(sr + beta * ld<AT>(vt[row]));
-            vp[row] = st<VT>(ri + beta * ld<AT>(vp[row]));
+          ALLREDUCE(0.0, s1, 0.0, 0.0);
+          rrs0 = out[1];
+        }
+        double rrs = rrs0;
+        if (rrs0 > 0.0) {
+          for (;;) {
+            // q = p - (S/alpha) t, with t = (S/alpha) p
+            double s0 = 0.0;
+            for (int t = t0; t < t1; ++t) {
+              const int row = t * BLOCK + tid;
+              const AT pi = ld<AT>(vp[row]);
+              const AT qv = pi - inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) { return ld<AT>(vt[c]); });
+              const VT qi = st<VT>(qv);
+              vq[row] = qi;
+              s0 += (double)pi * (double)ld<AT>(qi);
+            }
+            ALLREDUCE(s0, 0.0, 0.0, 0.0);
+            const double pqs = out[0];
+            if (!(pqs > 0.0) || !isfinite(pqs)) {
+              if (its == 0) status = isfinite(pqs) ? GADI_ENOTSPD : (Mode::id == GADI_PREC_FP16_IR ? GADI_EOVERFLOW16 : GADI_EDIVERGED);
+              break;
+            }
+            const AT ak = (AT)(rrs / pqs);
+            s0 = 0.0;
+            for (int t = t0; t < t1; ++t) {
+              const int row = t * BLOCK + tid;
+              const AT pi = ld<AT>(vp[row]);
+              w[row] = (its == 0 ? ST(0) : w[row]) + (ST)(ak * pi);
+              const VT ri = st<VT>(ld<AT>(vr[row]) - ak * ld<AT>(vq[row]));
+              vr[row] = ri;
+              const double dr = (double)ld<AT>(ri);
+              s0 += dr * dr;
+            }
+            ALLREDUCE(s0, 0.0, 0.0, 0.0);
+            const double rr_new = out[0];
+            ++its;
+            if (rr_new <= eps_s2 * rrs0 || its >= a.maxit_in || !isfinite(rr_new)) break;
+            const AT beta = (AT)(rr_new / rrs);
+            rrs = rr_new;
+            for (int t = t0; t < t1; ++t) {
+              const int row = t * BLOCK + tid;
+              const AT ri = ld<AT>(vr[row]);
+              const AT sr = inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) { return ld<AT>(vr[c]); });
+              vt[row] = st<VT>(sr + beta * ld<AT>(vt[row]));
+              vp[row] = st<VT>(ri + beta * ld<AT>(vp[row]));
+            }
+            ALLREDUCE(0.0, 0.0, 0.0, 0.0);
           }
-          ALLREDUCE(0.0, 0.0, 0.0, 0.0);
         }
       }
       is += its;
@@ -365,7 +563,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
         const double unscale = ldexp(1.0, e1 + e2);
         for (int t = t0; t < t1; ++t) {
           const int row = t * BLOCK + tid;
-          const AT ui = (AT)w[row] - inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) { return (AT)w[c]; });
+          const AT ui = (AT)wsol[row] - inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) { return (AT)wsol[c]; });
           x[row] += (double)ui * unscale;
         }
         ALLREDUCE(0.0, 0.0, 0.0, 0.0);

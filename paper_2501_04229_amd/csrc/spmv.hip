@@ -145,10 +145,12 @@ extern "C" gadi_status gadi_features(gadi_handle* h, int32_t dim, int32_t grid, 
   out[0] = (float)std::log((double)s.n);
   out[1] = (float)dim;
   out[2] = (float)std::log10(bmean);
-  out[3] = (float)(bmax * hgrid / 2.0);
+  // scale-free quantities enter in log10 (floored at 1e-12 so beta = 0 stays finite)
+  auto lg = [](double v) { return std::log10(v > 1e-12 ? v : 1e-12); };
+  out[3] = (float)lg(bmax * hgrid / 2.0);
   out[4] = (float)g0;
   out[5] = (float)g1;
-  out[6] = (float)g2;
-  out[7] = (float)g3;
+  out[6] = (float)lg(g2);
+  out[7] = (float)lg(g3);
   return GADI_OK;
 }

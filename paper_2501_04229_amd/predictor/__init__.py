@@ -15,9 +15,10 @@ Ties go to fewer outer sweeps, then to the larger alpha.  Targets are
 (log10 alpha, omega).
 
 The default parameters (0.5, 0.5) are both the fallback and the judge:
-`solve_auto` runs the predicted parameters with a work budget equal to what
-the default needs (when known) and falls back to the default if the
-prediction fails or runs out of budget.
+`solve_auto` probes both for a few sweeps, projects each one's remaining time
+from its measured contraction rate, and continues the faster one from its own
+iterate, so a prediction that would need more time than the default is
+rejected at the cost of its probe.
 """
 from __future__ import annotations
 
@@ -132,17 +133,56 @@ def predict(p, system, A):
     return p.predict(f)
 
 
-def solve_auto(system, A, b, predictor, default_work=None, **kw):
-    """Solve with predicted (alpha, omega); fall back to the default parameters
-    if the prediction fails or needs more work than the default (when the
-    default's work is known).  Returns (x, info, used) with used in
-    {'mlp', 'default'} and info['fell_back'] set accordingly."""
+def _projected_sweeps(hist, tol):
+    """Sweeps still needed to reach RES <= tol, from the contraction rate fitted
+    (least squares on log RES) over the second half of a probe's history."""
+    h = np.asarray(hist, dtype=np.float64)
+    h = h[np.isfinite(h) & (h > 0)]
+    if len(h) < 4:
+        return math.inf
+    k = np.arange(len(h))[len(h) // 2:]
+    y = np.log(h[len(h) // 2:])
+    slope = np.polyfit(k, y, 1)[0]
+    if not slope < 0:
+        return math.inf
+    return max(0.0, (math.log(tol) - math.log(h[-1])) / slope)
+
+
+def solve_auto(system, A, b, predictor, tol=1e-10, probe=24, **kw):
+    """Solve with the predicted (alpha, omega), judged by the default (0.5, 0.5).
+
+    Both candidates run `probe` sweeps; each projects its remaining time from
+    its measured contraction rate and time per sweep; the one with the smaller
+    projection continues from its own iterate (warm start), so a rejected
+    prediction costs only its probe.  Returns (x, info, used) with used in
+    {'mlp', 'default'}; info sums sweeps, inner steps and device seconds over
+    every launch, and info['fell_back'] = 1 when the default was used."""
     a, w = predict(predictor, system, A)
-    x, info = system.solve(b, a, w, **kw)
-    if info["status"] == gadi.OK and (default_work is None or work(info) <= default_work):
-        info["fell_back"] = 0
-        return x, info, "mlp"
-    x2, info2 = system.solve(b, DEFAULT[0], DEFAULT[1], **kw)
-    info2["fell_back"] = 1
-    info2["seconds"] += info["seconds"]
-    return x2, info2, "default"
+    maxit = kw.pop("maxit_outer", 20000)
+    probe = min(probe, maxit)
+    cands = [(a, w, "mlp"), (DEFAULT[0], DEFAULT[1], "default")]
+    total = {"outer_sweeps": 0, "inner_H": 0, "inner_S": 0, "seconds": 0.0, "launches": 0}
+    probes = []
+    for al, om, tag in cands:
+        x, info = system.solve(b, al, om, tol=tol, maxit_outer=probe, history=True, **kw)
+        info["launches"] = 1
+        for k in total:
+            total[k] += info[k]
+        if info["status"] == gadi.OK:
+            info.update(total)
+            info["fell_back"] = int(tag == "default")
+            return x, info, tag
+        hist = system.history
+        proj = _projected_sweeps(hist, tol) if info["status"] == gadi.EMAXIT else math.inf
+        per = info["seconds"] / max(1, info["outer_sweeps"])
+        probes.append((proj * per, al, om, tag, x, hist[-1] if len(hist) else 1.0))
+    probes.sort(key=lambda p: p[0])
+    _, al, om, tag, x0, res_k = probes[0]
+    x, info = system.solve(b, al, om, tol=tol / max(res_k, 1e-300), x0=x0, maxit_outer=max(0, maxit - probe), **kw)
+    info["launches"] = 1
+    for k in total:
+        total[k] += info[k]
+    info.update(total)
+    info["relres"] = info["relres"] * res_k
+    info["fell_back"] = int(tag == "default")
+    return x, info, tag

@@ -7,9 +7,9 @@ beta ~ logU(1, 500) on all axes), b = A x* with x* ~ U(-1, 1) seeded per
 system.  Each system is solved with half-precision GADI-IR to RES <= 1e-10
 twice: with the default (0.5, 0.5) and with the predictor's (alpha, omega).
 Reported per system and as geometric means: outer sweeps, work (operator
-products) and device time, raw and with the fallback rule (a prediction that
-fails or needs more work than the default costs its own time plus the
-default solve).
+products) and device time of the raw prediction, and the device time of
+`solve_auto` (the prediction judged by the default: both probed, the faster
+projection continues from its own iterate).
 """
 from __future__ import annotations
 
@@ -45,20 +45,23 @@ def evaluate(predictor, count=40, nmin=96, nmax=192, tol=1e-10, maxit_outer=2000
         a, w = pr.predict(predictor, g, A)
         xd, idf = g.solve(b, pr.DEFAULT[0], pr.DEFAULT[1], tol=tol, maxit_outer=maxit_outer)
         xm, iml = g.solve(b, a, w, tol=tol, maxit_outer=maxit_outer)
-        ok_m = iml["status"] == gadi.OK and pr.work(iml) <= pr.work(idf)
-        fb_seconds = iml["seconds"] if ok_m else iml["seconds"] + idf["seconds"]
+        xa, iau, used = pr.solve_auto(g, A, b, predictor, tol=tol, maxit_outer=maxit_outer)
+        ok_m = used == "mlp"
+        fb_seconds = iau["seconds"]
         row = {"n": n, "beta": beta, "alpha": a, "omega": w,
                "default": {k: idf[k] for k in ("status", "outer_sweeps", "inner_H", "inner_S", "seconds")},
                "mlp": {k: iml[k] for k in ("status", "outer_sweeps", "inner_H", "inner_S", "seconds")},
                "default_work": pr.work(idf), "mlp_work": pr.work(iml), "fallback": not ok_m,
                "with_fallback_seconds": fb_seconds,
+               "auto": {k: iau[k] for k in ("status", "outer_sweeps", "inner_H", "inner_S", "seconds", "relres")},
+               "rel_err_auto": float(np.linalg.norm(xa - xs) / np.linalg.norm(xs)),
                "rel_err_mlp": float(np.linalg.norm(xm - xs) / np.linalg.norm(xs)),
                "rel_err_default": float(np.linalg.norm(xd - xs) / np.linalg.norm(xs))}
         rows.append(row)
         if log:
             print(f"# n={n} beta={beta:.3g} pred=({a:.3g},{w:.3g}) default {idf['outer_sweeps']} sweeps "
                   f"{idf['seconds']:.3f}s | mlp {iml['status_str']} {iml['outer_sweeps']} sweeps "
-                  f"{iml['seconds']:.3f}s", file=log, flush=True)
+                  f"{iml['seconds']:.3f}s | auto {used} {iau['seconds']:.3f}s", file=log, flush=True)
         g.close()
     conv = [r for r in rows if r["mlp"]["status"] == gadi.OK and r["default"]["status"] == gadi.OK]
     summary = {
@@ -72,6 +75,7 @@ def evaluate(predictor, count=40, nmin=96, nmax=192, tol=1e-10, maxit_outer=2000
         "gmean_seconds_mlp_raw": gmean([r["mlp"]["seconds"] for r in rows]),
         "gmean_seconds_mlp_with_fallback": gmean([r["with_fallback_seconds"] for r in rows]),
         "fallbacks": sum(r["fallback"] for r in rows),
+        "auto_failures": sum(r["auto"]["status"] != gadi.OK for r in rows),
         "mlp_failures": sum(r["mlp"]["status"] != gadi.OK for r in rows),
     }
     summary["speedup_time_with_fallback"] = summary["gmean_seconds_default"] / summary["gmean_seconds_mlp_with_fallback"]
