@@ -127,6 +127,9 @@ def main():
     ap.add_argument("--params", default="mlp", choices=["mlp", "default"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with one elementwise copy of 2^26 floats (reads and writes 256 MiB) "
+                         "to calibrate hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver is a single-GPU build.",
@@ -271,6 +274,12 @@ def main():
                      "launch_seconds_mean": float(np.sum(kernel_s)) / launches, "traffic": None},
         "cpu_baseline": cpu,
     }
+    if args.copy_calibration:
+        xc = torch.ones(1 << 26, device="cuda", dtype=torch.float32)
+        yc = torch.empty_like(xc)
+        torch.mul(xc, 1.0, out=yc)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 4 * (1 << 26)
     print(json.dumps(out), flush=True)
 
 

@@ -172,6 +172,11 @@ gadi_status gadi_mlp_set_weights(gadi_mlp* m, const float* w);
 gadi_status gadi_mlp_get_weights(gadi_mlp* m, float* w);
 /* feature standardisation: x_std = (x - mu) / sd, mu/sd [8] host */
 gadi_status gadi_mlp_set_norm(gadi_mlp* m, const float* mu, const float* sd);
+/* Feature range [lo, hi] (host [8] each): raw features are clamped to it before
+ * standardisation, so predictions never extrapolate beyond the training set.
+ * gadi_train_mlp sets it to the training features' range; default unbounded. */
+gadi_status gadi_mlp_set_bounds(gadi_mlp* m, const float* lo, const float* hi);
+gadi_status gadi_mlp_get_bounds(gadi_mlp* m, float* lo, float* hi);
 /* Read the standardisation in use (mu, sd [8] host out). */
 gadi_status gadi_mlp_get_norm(gadi_mlp* m, float* mu, float* sd);
 /* Forward pass on the device: X [B,8] host (raw features), Y [B,2] host out. */
@@ -182,7 +187,7 @@ gadi_status gadi_mlp_loss_grad(gadi_mlp* m, const float* Xs, const float* Y, int
                                float* grad);
 /* Train with Adam (beta1 0.9, beta2 0.999, eps 1e-8) for `epochs` full-batch
  * steps on raw features X [n,8] and targets Y [n,2] (host); computes and stores
- * the standardisation from X.  loss_out[epochs] (may be NULL) gets the loss
+ * the standardisation and the feature range from X.  loss_out[epochs] (may be NULL) gets the loss
  * before each step.  All arithmetic runs in the device kernels. */
 gadi_status gadi_train_mlp(gadi_mlp* m, const float* X, const float* Y, int32_t n, int32_t epochs,
                            float lr, float* loss_out);

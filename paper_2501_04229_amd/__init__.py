@@ -70,6 +70,8 @@ def _load():
         "gadi_mlp_get_weights": (i32, [vp, vp]),
         "gadi_mlp_set_norm": (i32, [vp, vp, vp]),
         "gadi_mlp_get_norm": (i32, [vp, vp, vp]),
+        "gadi_mlp_set_bounds": (i32, [vp, vp, vp]),
+        "gadi_mlp_get_bounds": (i32, [vp, vp, vp]),
         "gadi_mlp_forward": (i32, [vp, vp, i32, vp]),
         "gadi_mlp_loss_grad": (i32, [vp, vp, vp, i32, vp, vp]),
         "gadi_train_mlp": (i32, [vp, vp, vp, i32, i32, ctypes.c_float, vp]),
@@ -297,6 +299,19 @@ class Predictor:
         _check(_lib.gadi_mlp_get_norm(self._h, ctypes.c_void_p(mu.ctypes.data), ctypes.c_void_p(sd.ctypes.data)),
                "get_norm")
         return mu, sd
+
+    def set_bounds(self, lo, hi):
+        lo = np.ascontiguousarray(lo, dtype=np.float32)
+        hi = np.ascontiguousarray(hi, dtype=np.float32)
+        _check(_lib.gadi_mlp_set_bounds(self._h, ctypes.c_void_p(lo.ctypes.data), ctypes.c_void_p(hi.ctypes.data)),
+               "set_bounds")
+
+    def bounds(self):
+        lo = np.zeros(8, np.float32)
+        hi = np.zeros(8, np.float32)
+        _check(_lib.gadi_mlp_get_bounds(self._h, ctypes.c_void_p(lo.ctypes.data), ctypes.c_void_p(hi.ctypes.data)),
+               "get_bounds")
+        return lo, hi
 
     def forward(self, X):
         X = np.ascontiguousarray(X, dtype=np.float32)

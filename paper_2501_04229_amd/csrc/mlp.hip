@@ -49,11 +49,11 @@ struct gadi_mlp {
   float* g = nullptr;     // [kNP]
   float* m = nullptr;     // Adam first moment
   float* v = nullptr;     // Adam second moment
-  float* norm = nullptr;  // [16]: mu[8], sd[8]
+  float* norm = nullptr;  // [32]: mu[8], sd[8], lo[8], hi[8]
   float* loss = nullptr;  // [epochs] or [1]
   int* step = nullptr;    // Adam step counter (device)
   int loss_cap = 0;
-  float hnorm[16];
+  float hnorm[32];
   gadi::MlpBuf buf;
 };
 
@@ -178,14 +178,22 @@ __global__ void step_kernel(int* step) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *step += 1;
 }
 
-// Column mean and standard deviation of raw features (zero-variance columns
-// get scale 1), then in-place standardisation.
+// Column mean, standard deviation (zero-variance columns get scale 1), minimum
+// and maximum of raw features, then in-place standardisation.
 __global__ void norm_kernel(float* __restrict__ X, int n, float* __restrict__ norm) {
   const int c = threadIdx.x;
   if (c < kIn) {
     double mu = 0.0;
-    for (int i = 0; i < n; ++i) mu += X[(size_t)i * kIn + c];
+    float lo = X[c], hi = X[c];
+    for (int i = 0; i < n; ++i) {
+      const float v = X[(size_t)i * kIn + c];
+      mu += v;
+      lo = fminf(lo, v);
+      hi = fmaxf(hi, v);
+    }
     mu /= n;
+    norm[2 * kIn + c] = lo;
+    norm[3 * kIn + c] = hi;
     double var = 0.0;
     for (int i = 0; i < n; ++i) {
       const double d = X[(size_t)i * kIn + c] - mu;
@@ -203,10 +211,13 @@ __global__ void norm_kernel(float* __restrict__ X, int n, float* __restrict__ no
   }
 }
 
+// Raw features are clamped to the range seen in training (the network is not
+// asked to extrapolate), then standardised.
 __global__ void apply_norm_kernel(float* __restrict__ X, int n, const float* __restrict__ norm) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n * kIn; i += gridDim.x * blockDim.x) {
     const int c = i % kIn;
-    X[i] = (X[i] - norm[c]) / norm[kIn + c];
+    const float v = fminf(fmaxf(X[i], norm[2 * kIn + c]), norm[3 * kIn + c]);
+    X[i] = (v - norm[c]) / norm[kIn + c];
   }
 }
 
@@ -259,7 +270,7 @@ extern "C" gadi_status gadi_mlp_create(uint64_t seed, gadi_mlp** out) {
   if (e == hipSuccess) e = hipMalloc((void**)&m->g, sizeof(float) * kNP);
   if (e == hipSuccess) e = hipMalloc((void**)&m->m, sizeof(float) * kNP);
   if (e == hipSuccess) e = hipMalloc((void**)&m->v, sizeof(float) * kNP);
-  if (e == hipSuccess) e = hipMalloc((void**)&m->norm, sizeof(float) * 16);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->norm, sizeof(float) * 32);
   if (e == hipSuccess) e = hipMalloc((void**)&m->step, sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&m->loss, sizeof(float));
   if (e != hipSuccess) {
@@ -283,9 +294,11 @@ extern "C" gadi_status gadi_mlp_create(uint64_t seed, gadi_mlp** out) {
   for (int i = 0; i < kIn; ++i) {
     m->hnorm[i] = 0.f;
     m->hnorm[kIn + i] = 1.f;
+    m->hnorm[2 * kIn + i] = -INFINITY;
+    m->hnorm[3 * kIn + i] = INFINITY;
   }
   e = hipMemcpy(m->w, w.data(), sizeof(float) * kNP, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(m->norm, m->hnorm, sizeof(float) * 16, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->norm, m->hnorm, sizeof(float) * 32, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     gadi_mlp_destroy(m);
     return fail_hip(e, "gadi_mlp_create", __FILE__, __LINE__);
@@ -323,7 +336,27 @@ extern "C" gadi_status gadi_mlp_set_norm(gadi_mlp* m, const float* mu, const flo
     m->hnorm[i] = mu[i];
     m->hnorm[kIn + i] = sd[i];
   }
-  GADI_HIP_CHECK(hipMemcpy(m->norm, m->hnorm, sizeof(float) * 16, hipMemcpyHostToDevice));
+  GADI_HIP_CHECK(hipMemcpy(m->norm, m->hnorm, sizeof(float) * 32, hipMemcpyHostToDevice));
+  return GADI_OK;
+}
+
+extern "C" gadi_status gadi_mlp_set_bounds(gadi_mlp* m, const float* lo, const float* hi) {
+  if (!m || !lo || !hi) return GADI_EINVAL;
+  for (int i = 0; i < kIn; ++i) {
+    if (!(lo[i] <= hi[i])) return GADI_EINVAL;
+    m->hnorm[2 * kIn + i] = lo[i];
+    m->hnorm[3 * kIn + i] = hi[i];
+  }
+  GADI_HIP_CHECK(hipMemcpy(m->norm, m->hnorm, sizeof(float) * 32, hipMemcpyHostToDevice));
+  return GADI_OK;
+}
+
+extern "C" gadi_status gadi_mlp_get_bounds(gadi_mlp* m, float* lo, float* hi) {
+  if (!m || !lo || !hi) return GADI_EINVAL;
+  for (int i = 0; i < kIn; ++i) {
+    lo[i] = m->hnorm[2 * kIn + i];
+    hi[i] = m->hnorm[3 * kIn + i];
+  }
   return GADI_OK;
 }
 
@@ -379,7 +412,7 @@ extern "C" gadi_status gadi_train_mlp(gadi_mlp* m, const float* X, const float* 
   GADI_HIP_CHECK(hipMemcpy(m->buf.Y, Y, sizeof(float) * n * kOut, hipMemcpyHostToDevice));
   hipLaunchKernelGGL(norm_kernel, dim3(1), dim3(256), 0, 0, m->buf.X, n, m->norm);
   GADI_HIP_CHECK(hipGetLastError());
-  GADI_HIP_CHECK(hipMemcpy(m->hnorm, m->norm, sizeof(float) * 16, hipMemcpyDeviceToHost));
+  GADI_HIP_CHECK(hipMemcpy(m->hnorm, m->norm, sizeof(float) * 32, hipMemcpyDeviceToHost));
   GADI_HIP_CHECK(hipMemset(m->m, 0, sizeof(float) * kNP));
   GADI_HIP_CHECK(hipMemset(m->v, 0, sizeof(float) * kNP));
   GADI_HIP_CHECK(hipMemset(m->step, 0, sizeof(int)));

@@ -109,15 +109,43 @@ def dataset(recs, feats):
     return np.asarray(X, np.float32), np.asarray(Y, np.float32)
 
 
-def train(X, Y, epochs=3000, lr=3e-3, seed=0):
+def fit(X, Y, epochs=None, lr=3e-3, seed=0, candidates=(100, 200, 400, 800, 1600, 3200), holdout=0.25):
+    """Train the predictor on the device.
+
+    With epochs=None the epoch count is chosen on a held-out split (a seeded
+    quarter of the systems): each candidate count trains a fresh network on
+    the rest, the one with the lowest held-out loss wins, and the final
+    network is trained on everything with that count.  Returns (predictor,
+    per-epoch training losses) and records the choice in `fit.last`."""
+    X = np.asarray(X, np.float32)
+    Y = np.asarray(Y, np.float32)
+    val = None
+    if epochs is None:
+        rng = np.random.default_rng(seed + 7)
+        idx = rng.permutation(len(X))
+        k = max(1, int(holdout * len(X)))
+        va, tr = idx[:k], idx[k:]
+        val = {}
+        for e in candidates:
+            p = gadi.Predictor(seed=seed)
+            p.train(X[tr], Y[tr], epochs=e, lr=lr)
+            d = p.forward(X[va]) - Y[va]
+            val[e] = float(np.mean(d * d))
+            p.close()
+        epochs = min(val, key=val.get)
     p = gadi.Predictor(seed=seed)
     losses = p.train(X, Y, epochs=epochs, lr=lr)
+    fit.last = {"epochs": int(epochs), "holdout_loss": val}
     return p, losses
+
+
+fit.last = {}
 
 
 def save(p, path=WEIGHTS, **meta):
     mu, sd = p.norm()
-    np.savez(path, weights=p.weights(), mu=mu, sd=sd, **meta)
+    lo, hi = p.bounds()
+    np.savez(path, weights=p.weights(), mu=mu, sd=sd, lo=lo, hi=hi, **meta)
 
 
 def load(path=WEIGHTS):
@@ -125,6 +153,8 @@ def load(path=WEIGHTS):
     p = gadi.Predictor()
     p.set_weights(d["weights"])
     p.set_norm(d["mu"], d["sd"])
+    if "lo" in d:
+        p.set_bounds(d["lo"], d["hi"])
     return p
 
 
@@ -135,25 +165,28 @@ def predict(p, system, A):
 
 def _projected_sweeps(hist, tol):
     """Sweeps still needed to reach RES <= tol, from the contraction rate fitted
-    (least squares on log RES) over the second half of a probe's history."""
+    (least squares on log RES) over the last third of a probe's history (the
+    early sweeps contract fast modes and overstate the rate)."""
     h = np.asarray(hist, dtype=np.float64)
     h = h[np.isfinite(h) & (h > 0)]
-    if len(h) < 4:
+    if len(h) < 6:
         return math.inf
-    k = np.arange(len(h))[len(h) // 2:]
-    y = np.log(h[len(h) // 2:])
+    k0 = (2 * len(h)) // 3
+    k = np.arange(len(h))[k0:]
+    y = np.log(h[k0:])
     slope = np.polyfit(k, y, 1)[0]
     if not slope < 0:
         return math.inf
     return max(0.0, (math.log(tol) - math.log(h[-1])) / slope)
 
 
-def solve_auto(system, A, b, predictor, tol=1e-10, probe=24, **kw):
+def solve_auto(system, A, b, predictor, tol=1e-10, probe=48, margin=0.9, **kw):
     """Solve with the predicted (alpha, omega), judged by the default (0.5, 0.5).
 
     Both candidates run `probe` sweeps; each projects its remaining time from
-    its measured contraction rate and time per sweep; the one with the smaller
-    projection continues from its own iterate (warm start), so a rejected
+    its measured contraction rate and time per sweep; the prediction is kept
+    only if its projection is below `margin` times the default's, and the kept
+    candidate continues from its own iterate (warm start), so a rejected
     prediction costs only its probe.  Returns (x, info, used) with used in
     {'mlp', 'default'}; info sums sweeps, inner steps and device seconds over
     every launch, and info['fell_back'] = 1 when the default was used."""
@@ -176,8 +209,10 @@ def solve_auto(system, A, b, predictor, tol=1e-10, probe=24, **kw):
         proj = _projected_sweeps(hist, tol) if info["status"] == gadi.EMAXIT else math.inf
         per = info["seconds"] / max(1, info["outer_sweeps"])
         probes.append((proj * per, al, om, tag, x, hist[-1] if len(hist) else 1.0))
-    probes.sort(key=lambda p: p[0])
-    _, al, om, tag, x0, res_k = probes[0]
+    # the prediction must beat the default's projection by a margin to be kept
+    pm = next(p for p in probes if p[3] == "mlp")
+    pd = next(p for p in probes if p[3] == "default")
+    _, al, om, tag, x0, res_k = pm if pm[0] < margin * pd[0] else pd
     x, info = system.solve(b, al, om, tol=tol / max(res_k, 1e-300), x0=x0, maxit_outer=max(0, maxit - probe), **kw)
     info["launches"] = 1
     for k in total:

@@ -39,29 +39,53 @@ def build_family(count):
     return metas, rhs
 
 
+def load_table(path):
+    """Records (list of per-trial dicts per system) and features from a sweep table."""
+    d = np.load(path)
+    keys = ["status", "outer_sweeps", "inner_H", "inner_S", "relres", "seconds", "alpha", "omega"]
+    recs = []
+    for i in range(d["status"].shape[0]):
+        row = []
+        for t in range(d["status"].shape[1]):
+            if np.isnan(d["status"][i, t]):
+                continue
+            row.append({k: (int(d[k][i, t]) if k in ("status", "outer_sweeps", "inner_H", "inner_S")
+                            else float(d[k][i, t])) for k in keys})
+        recs.append(row)
+    return recs, d["features"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--systems", type=int, default=256)
-    ap.add_argument("--epochs", type=int, default=3000)
+    ap.add_argument("--epochs", type=int, default=None,
+                    help="fixed epoch count (default: chosen on a held-out quarter)")
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--out", default=pr.WEIGHTS)
     ap.add_argument("--table", default=TABLE)
+    ap.add_argument("--from-table", action="store_true",
+                    help="train from an existing sweep table instead of sweeping again")
     args = ap.parse_args()
     t0 = time.time()
-    metas, rhs = build_family(args.systems)
-    t1 = time.time()
-    recs, feats = pr.sweep_table(metas, rhs, maxit_outer=args.maxit)
-    t2 = time.time()
+    if args.from_table:
+        recs, feats = load_table(args.table)
+        t1 = t2 = time.time()
+    else:
+        metas, rhs = build_family(args.systems)
+        t1 = time.time()
+        recs, feats = pr.sweep_table(metas, rhs, maxit_outer=args.maxit)
+        t2 = time.time()
     X, Y = pr.dataset(recs, feats)
-    p, losses = pr.train(X, Y, epochs=args.epochs, lr=args.lr)
+    p, losses = pr.fit(X, Y, epochs=args.epochs, lr=args.lr)
     t3 = time.time()
     keys = ["status", "outer_sweeps", "inner_H", "inner_S", "relres", "seconds", "alpha", "omega"]
     width = max(len(row) for row in recs)
     table = {k: np.array([[row[t][k] if t < len(row) else np.nan for t in range(width)] for row in recs])
              for k in keys}
-    np.savez(args.table, features=feats, **table)
-    pr.save(p, args.out, train_loss=losses)
+    if not args.from_table:
+        np.savez(args.table, features=feats, **table)
+    pr.save(p, args.out, train_loss=losses, epochs=pr.fit.last["epochs"])
     conv = int(np.nansum(table["status"] == 0))
     lab = [pr.label(r) for r in recs]
     hist = {}
@@ -69,10 +93,11 @@ def main():
         if t is not None:
             key = f"{row[t]['alpha']:.2g},{row[t]['omega']:.2g}"
             hist[key] = hist.get(key, 0) + 1
-    print(json.dumps({"systems": len(metas), "trials": len(metas) * 16, "converged_trials": conv,
+    print(json.dumps({"systems": len(recs), "trials": len(recs) * 16, "converged_trials": conv,
                       "labelled_systems": int(len(X)), "label_histogram": hist,
                       "sweep_seconds": t2 - t1, "gen_seconds": t1 - t0, "train_seconds": t3 - t2,
-                      "loss_first": float(losses[0]), "loss_last": float(losses[-1])}), flush=True)
+                      "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+                      "epochs": pr.fit.last["epochs"], "holdout_loss": pr.fit.last["holdout_loss"]}), flush=True)
 
 
 if __name__ == "__main__":

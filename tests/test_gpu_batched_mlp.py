@@ -150,3 +150,30 @@ def test_mlp_training_fits_and_predicts_in_range():
     a, w = p.predict(X[0])
     assert 1e-3 <= a <= 10.0 and 0.0 <= w <= 1.99
     assert abs(np.log10(a) - Y[0, 0]) < 0.15 and abs(w - Y[0, 1]) < 0.1
+
+
+def test_mlp_inputs_clamped_to_training_range():
+    """Raw features outside [lo, hi] give the prediction of the clamped features."""
+    th, X, Y = _rand_problem(6, 4)
+    p = gadi.Predictor()
+    p.set_weights(th)
+    p.set_norm(np.zeros(8), np.ones(8))
+    lo, hi = -np.ones(8, np.float32), np.ones(8, np.float32)
+    p.set_bounds(lo, hi)
+    Xo = (X * 5).astype(np.float32)
+    y = p.forward(Xo)
+    yref, _ = omlp.forward(th.astype(np.float64), np.clip(Xo, lo, hi).astype(np.float64))
+    assert np.allclose(y, yref, rtol=1e-5, atol=1e-5 * np.abs(yref).max())
+    with pytest.raises(gadi.GadiError):
+        p.set_bounds(hi, lo)
+
+
+def test_trained_predictor_stays_in_grid_range():
+    """The committed weights predict alpha and omega inside the trial grid's span for the bench systems."""
+    from paper_2501_04229_amd import predictor as pr
+    p = pr.load()
+    for n, dim, beta in ((128, 3, 20.0), (64, 2, 10.0), (40, 3, 300.0)):
+        A = gi.convdiff(n, dim, beta)
+        g = gadi.System(A)
+        a, w = pr.predict(p, g, A)
+        assert 1e-3 <= a <= 10.0 and 0.0 <= w <= 1.99
