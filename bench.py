@@ -29,23 +29,27 @@ HBM_PEAK_GBS = 8000.0
 WEIGHTS = os.path.join(ROOT, "paper_2501_04229_amd", "predictor", "mlp_weights.npz")
 
 
-def solve_bytes(prec: str, n: int, z: int, zs: int, sweeps: int, inner_h: int, inner_s: int) -> float:
-    """Algorithmic HBM bytes of one solve launch.
+def solve_bytes(prec: str, L: dict, sweeps: int, inner_h: int, inner_s: int, launches: int = 1) -> float:
+    """Algorithmic HBM bytes of solve-kernel launches with the given iteration counts.
 
-    Per unit (value + int32 index per stored entry, each vector read or written once):
-      residual a1          12 z + 22 N   (A in double, x/b in double, scaled half output)
-      update a6            6 z_S + 26 N  (one S product on the half CGNE solution + x read/write)
-      CG step on alpha I+H     6 z + 16 N   (half values)      | 12 z + 32 N (double)
-      CGNE step on alpha I+S   12 z_S + 16 N (two S products)  | 24 z_S + 32 N (double)
-    One residual more than corrections is evaluated (the converged one)."""
-    if prec == "fp64":
-        cg, cgne, upd = 12 * z + 32 * n, 24 * zs + 32 * n, 12 * zs + 32 * n
-    elif prec == "fp32":
-        cg, cgne, upd = 8 * z + 24 * n, 16 * zs + 24 * n, 8 * zs + 30 * n
-    else:
-        cg, cgne, upd = 6 * z + 16 * n, 12 * zs + 16 * n, 6 * zs + 26 * n
-    res = 12 * z + 22 * n
-    return float((sweeps + 1) * res + sweeps * upd + inner_h * cg + inner_s * cgne)
+    Matrix streams follow the packed layout (L = System.layout()): one value per
+    structural entry plus an int32 column for entries of explicit slices
+    (diagonal-style slices store no column).  Per unit, with N rows, z_o
+    off-diagonal entries, z_e of them in explicit slices, v = value/vector bytes
+    (2 fp16, 4 fp32, 8 fp64), s = inner accumulator bytes (4, or 8 in fp64):
+      residual a1          8 (z_o + N) + 4 z_e + 22 N      (double A, x, b; scaled output)
+      CG step              v (z_o + N) + 4 z_e + 8 v N     (alpha I + H product, 8 vector accesses)
+      CGNE step            2 (v z_o + 4 z_e + 4 v N)       (two S products)
+      update a6            v z_o + 4 z_e + 16 N + 2 s N    (one S product, x read/write)
+    Each launch evaluates one residual more than it applies corrections."""
+    v = {"fp16": 2, "fp32": 4, "fp64": 8}[prec]
+    sb = 8 if prec == "fp64" else 4
+    n, zo, ze = L["n"], L["nnz_off"], L["explicit_entries"]
+    res = 8 * (zo + n) + 4 * ze + 22 * n
+    cg = v * (zo + n) + 4 * ze + 8 * v * n
+    cgne = 2 * (v * zo + 4 * ze + 4 * v * n)
+    upd = v * zo + 4 * ze + 16 * n + 2 * sb * n
+    return float((sweeps + launches) * res + sweeps * upd + inner_h * cg + inner_s * cgne)
 
 
 def load_predictor():
@@ -85,7 +89,8 @@ def cpu_baseline(A, b, alpha, omega, sweeps_needed, eps, budget_s=20.0):
 
 
 def spmv_gbs(g, A, alpha, reps=50):
-    """Stand-alone fp16 (alpha I + H) product: algorithmic 6 z + 8 N bytes per launch."""
+    """Stand-alone products: fp16 (alpha I + H) x moves 2 (z_o + N) + 4 z_e + 4 N
+    algorithmic bytes, fp64 A x moves 8 (z_o + N) + 4 z_e + 16 N."""
     import torch
     n = A.n
     x = torch.rand(n, device="cuda", dtype=torch.float16)
@@ -100,7 +105,8 @@ def spmv_gbs(g, A, alpha, reps=50):
     e1.record()
     torch.cuda.synchronize()
     dt = e0.elapsed_time(e1) * 1e-3 / reps
-    by = 6.0 * A.nnz + 8.0 * n
+    L = g.layout()
+    by = 2.0 * (L["nnz_off"] + n) + 4.0 * L["explicit_entries"] + 4.0 * n
     y64 = torch.empty(n, device="cuda", dtype=torch.float64)
     x64 = torch.rand(n, device="cuda", dtype=torch.float64)
     for _ in range(5):
@@ -111,7 +117,7 @@ def spmv_gbs(g, A, alpha, reps=50):
     e1.record()
     torch.cuda.synchronize()
     dt64 = e0.elapsed_time(e1) * 1e-3 / reps
-    by64 = 12.0 * A.nnz + 20.0 * n
+    by64 = 8.0 * (L["nnz_off"] + n) + 4.0 * L["explicit_entries"] + 16.0 * n
     return {"fp16_H_us": dt * 1e6, "fp16_H_GBs": by / dt / 1e9, "fp64_A_us": dt64 * 1e6,
             "fp64_A_GBs": by64 / dt64 / 1e9}
 
@@ -190,14 +196,18 @@ def main():
     info = infos[-1]
     if info["status"] != gadi.OK:
         print(f"# solve did not converge: {info}", file=sys.stderr, flush=True)
+    prof = g.phase_profile()
+    print("# phase profile (block 0 compute s, count): " +
+          ", ".join(f"{k} {v[0]:.4f}/{v[1]}" for k, v in prof.items() if v[1]), file=sys.stderr, flush=True)
     xh = x.cpu().numpy()
     rel_err_xstar = float(np.linalg.norm(xh - xs) / np.linalg.norm(xs))
     kern = float(np.mean(kernel_s))
     # every solve-kernel launch of the timed region: total algorithmic bytes / total device time
+    lay = g.layout()
     tot_bytes = 0.0
     for inf in infos:
-        tot_bytes += solve_bytes(args.prec, n, z, zs, inf["outer_sweeps"], inf["inner_H"], inf["inner_S"])
-    tot_bytes += (launches - len(infos)) * (12.0 * z + 22.0 * n)  # one extra residual per extra launch
+        tot_bytes += solve_bytes(args.prec, lay, inf["outer_sweeps"], inf["inner_H"], inf["inner_S"],
+                                 inf.get("launches", 1))
     nbytes = tot_bytes / launches
     achieved = tot_bytes / float(np.sum(kernel_s)) / 1e9
     print(f"# fp16-IR: {step_s:.3f}s/solve, kernel {kern:.3f}s, {achieved:.0f} GB/s algorithmic, "
@@ -222,7 +232,7 @@ def main():
         torch.cuda.synchronize()
         wall64 = time.perf_counter() - tf0
         x64h = x64.cpu().numpy()
-        nb64 = solve_bytes("fp64", n, z, zs, i64["outer_sweeps"], i64["inner_H"], i64["inner_S"])
+        nb64 = solve_bytes("fp64", lay, i64["outer_sweeps"], i64["inner_H"], i64["inner_S"])
         fp64 = {"seconds": i64["seconds"], "wall_seconds": wall64, "status": i64["status_str"],
                 "sweeps": i64["outer_sweeps"],
                 "inner_H": i64["inner_H"], "inner_S": i64["inner_S"], "relres": i64["relres"],
@@ -255,6 +265,7 @@ def main():
         "dtype": {"fp16": "fp16 storage / fp32 arithmetic inner, f64 residual+update",
                   "fp32": "f32 inner, f64 residual+update", "fp64": "f64"}[args.prec],
         "data": "synthetic",
+        "layout": lay,
         "config": {"workload": args.workload, "N": n, "nnz": z, "tol": 1e-10,
                    "eps_inner": eps if eps is not None else (1e-6 if args.prec == "fp64" else 1e-3),
                    "alpha_predicted": alpha, "omega_predicted": omega, "params": psrc, "used": used,
@@ -268,6 +279,7 @@ def main():
         "fp64_gadi": fp64,
         "speedup_vs_fp64_gadi": (fp64["wall_seconds"] / step_s) if fp64 else None,
         "spmv": sp,
+        "phase_profile_last_launch": {k: {"seconds": v[0], "count": v[1]} for k, v in prof.items() if v[1]},
         "roofline": {"bound": "hbm", "kernel": f"solve_kernel<{args.prec}>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "algorithmic_bytes_per_launch": nbytes, "launches": launches,

@@ -10,6 +10,7 @@ from .convdiff import (  # noqa: F401
     Csr,
     convdiff,
     convdiff_nnz,
+    convdiff_skew_perturbed,
     csr_matvec,
     rhs_for,
     workload,

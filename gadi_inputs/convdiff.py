@@ -109,6 +109,31 @@ def convdiff(n: int, dim: int, beta) -> Csr:
     return Csr(N, row_ptr.astype(np.int32), col, val, dim=dim, grid=n, beta=beta_t)
 
 
+def convdiff_skew_perturbed(n: int, dim: int, beta, extra_per_row: float, scale: float, seed: int,
+                            rows_fraction: float = 1.0) -> Csr:
+    """Convection-diffusion matrix plus a random skew-symmetric perturbation
+    scale * (R - R^T), R with about `extra_per_row` random off-diagonal entries
+    in a `rows_fraction` of the rows.  H = (A + A^T)/2 is unchanged (still SPD),
+    the pattern is irregular: an input for the explicit-column storage path."""
+    import scipy.sparse as sp
+    A = convdiff(n, dim, beta).to_scipy().tocoo()
+    N = A.shape[0]
+    rng = np.random.default_rng(seed)
+    rows = np.flatnonzero(rng.random(N) < rows_fraction)
+    k = int(round(extra_per_row * len(rows)))
+    ri = rng.choice(rows, size=k) if len(rows) else np.zeros(0, dtype=np.int64)
+    ci = rng.integers(0, N, size=k)
+    keep = ri != ci
+    ri, ci = ri[keep], ci[keep]
+    v = rng.uniform(-1.0, 1.0, size=len(ri))
+    R = sp.coo_matrix((v, (ri, ci)), shape=(N, N)).tocsr()
+    M = (A.tocsr() + scale * (R - R.T)).tocsr()
+    M.sum_duplicates()
+    M.sort_indices()
+    return Csr(N, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64),
+               dim=dim, grid=n, beta=_beta_tuple(beta, dim))
+
+
 def csr_matvec(A: Csr, x: np.ndarray) -> np.ndarray:
     """y = A x in float64 (used only to manufacture right-hand sides)."""
     return A.to_scipy() @ np.asarray(x, dtype=np.float64)

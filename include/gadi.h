@@ -201,6 +201,19 @@ gadi_status gadi_destroy(gadi_handle* h);
 /* Static description of a status code. */
 const char* gadi_status_str(gadi_status s);
 
+/* Per-phase profile of the last gadi_ir_solve on the handle, measured by block
+ * 0 of the solve kernel (compute time between reductions, barrier waits
+ * excluded): seconds[10] and counts[10] for the phases 0 residual, 1 CG
+ * start, 2 CG product, 3 CG update, 4 CGNE start, 5 CGNE first product,
+ * 6 CGNE second product, 7 CGNE update, 8 solution update, 9 unused. */
+gadi_status gadi_get_phase_profile(gadi_handle* h, double* seconds, int64_t* counts);
+
+/* Device layout of the packed matrices, out[6] = {n, padded rows, off-diagonal
+ * entries of the union pattern of A and A^T, stored slots (entries plus
+ * padding / phantom zeros), stored slots in diagonal-style slices (no column
+ * index stored), structural entries in explicit slices (int32 column each)}. */
+gadi_status gadi_get_layout(gadi_handle* h, int64_t* out);
+
 /* Launch shape of the last gadi_ir_solve on this handle: returns the number of
  * blocks and stores the threads per block in *threads (may be NULL); 0 before
  * the first solve.  The shape is chosen per handle and precision by a timed

@@ -63,6 +63,8 @@ def _load():
                                         P(SolveInfo)]),
         "gadi_spmv": (i32, [vp, i32, f64, vp, vp]),
         "gadi_get_split_fp16": (i32, [vp, i32, vp, vp, vp, P(i64)]),
+        "gadi_get_layout": (i32, [vp, P(i64)]),
+        "gadi_get_phase_profile": (i32, [vp, P(f64), P(i64)]),
         "gadi_features": (i32, [vp, i32, i32, P(f64), P(ctypes.c_float)]),
         "gadi_mlp_create": (i32, [ctypes.c_uint64, P(vp)]),
         "gadi_mlp_destroy": (i32, [vp]),
@@ -213,6 +215,22 @@ class System:
                                         ctypes.c_void_p(col.ctypes.data), ctypes.c_void_p(val.ctypes.data),
                                         ctypes.byref(nnz)), "split")
         return rp, col, val.view(np.float16)
+
+    PHASES = ("residual", "cg_start", "cg_product", "cg_update", "cgne_start", "cgne_product1",
+              "cgne_product2", "cgne_update", "x_update")
+
+    def phase_profile(self):
+        """Block 0's compute seconds and counts per phase of the last solve."""
+        sec = (ctypes.c_double * 10)()
+        cnt = (ctypes.c_int64 * 10)()
+        _check(_lib.gadi_get_phase_profile(self._h, sec, cnt), "gadi_get_phase_profile")
+        return {k: (sec[i], cnt[i]) for i, k in enumerate(self.PHASES)}
+
+    def layout(self):
+        """Packed layout counts: dict with n, npad, nnz_off, slots, dia_slots, explicit_entries."""
+        out = (ctypes.c_int64 * 6)()
+        _check(_lib.gadi_get_layout(self._h, out), "gadi_get_layout")
+        return dict(zip(("n", "npad", "nnz_off", "slots", "dia_slots", "explicit_entries"), list(out)))
 
     def features(self, dim, grid, beta):
         beta = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, dtype=np.float64), (dim,)))

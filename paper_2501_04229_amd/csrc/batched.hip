@@ -28,6 +28,8 @@ struct BatchSys {
   int n, npad;
   const int32_t* slice_ptr;
   const int32_t* col;
+  const int32_t* slice_dia;
+  const int32_t* dia_off;
   const double* a_off;
   const double* a_diag;
   const void* h_off;
@@ -79,6 +81,8 @@ __global__ void __launch_bounds__(BLOCK) batched_kernel(BatchArgs ba) {
     a.hist_cap = 0;
     a.slice_ptr = S.slice_ptr;
     a.col = S.col;
+    a.slice_dia = S.slice_dia;
+    a.dia_off = S.dia_off;
     a.a_off = S.a_off;
     a.a_diag = S.a_diag;
     a.h_off = S.h_off;
@@ -250,6 +254,8 @@ extern "C" gadi_status gadi_ir_solve_batched(gadi_handle* const* hs, int32_t nsy
     d.npad = S.npad;
     d.slice_ptr = S.slice_ptr;
     d.col = S.col;
+    d.slice_dia = S.slice_dia;
+    d.dia_off = S.dia_off;
     d.a_off = S.a_off;
     d.a_diag = S.a_diag;
     if (o.prec == GADI_PREC_FP16_IR) {

@@ -77,9 +77,19 @@ __device__ __forceinline__ VT st(AT v) {
   return Cvt<VT>::template to<AT>(v);
 }
 
-// Off-diagonal part of one row of a SELL-64 operator: sum_j val_ij * fetch(col_ij)
-// over the row's slots in ascending column order.  W slots, unrolled so that
-// every index and value load is issued before the first gather.
+// Sparsity pattern shared by A, H and S in the packed layout (internal.h).
+struct Pattern {
+  const int32_t* sp;    // slice_ptr
+  const int32_t* col;   // explicit slices only
+  const int32_t* dia;   // offsets per diagonal-style slice, 0 = explicit
+  const int32_t* doff;  // [nslices * kDiaMax] column offsets
+  int nmax;             // last valid column (n - 1)
+};
+
+// Off-diagonal part of one row of an explicit SELL-64 slice:
+// sum_j val_ij * fetch(col_ij) over the row's slots in ascending column
+// order.  W slots, unrolled so that every index and value load is issued
+// before the first gather.
 template <int W, class AT, class MT, class F>
 __device__ __forceinline__ AT row_sum_w(int k0, const int32_t* __restrict__ col, const MT* __restrict__ val,
                                         F&& fetch) {
@@ -96,14 +106,53 @@ __device__ __forceinline__ AT row_sum_w(int k0, const int32_t* __restrict__ col,
   return acc;
 }
 
+// The same for a diagonal-style slice: the column of slot j is row + offs[j]
+// (offs wave-uniform), clamped into [0, nmax] so that phantom entries (value
+// 0) never address outside the vector.
+template <int W, class AT, class MT, class F>
+__device__ __forceinline__ AT row_sum_dia_w(int row, int k0, const int32_t* __restrict__ offs, int nmax,
+                                            const MT* __restrict__ val, F&& fetch) {
+  int c[W];
+  MT v[W];
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    v[j] = val[k0 + j * kSlice];
+    const int cc = row + offs[j];
+    c[j] = cc < 0 ? 0 : (cc > nmax ? nmax : cc);
+  }
+  AT acc = 0;
+#pragma unroll
+  for (int j = 0; j < W; ++j) acc += ld<AT>(v[j]) * fetch(c[j]);
+  return acc;
+}
+
 template <class AT, class MT, class F>
-__device__ __forceinline__ AT row_sum(int row, const int32_t* __restrict__ slice_ptr,
-                                      const int32_t* __restrict__ col, const MT* __restrict__ val, F&& fetch) {
+__device__ __forceinline__ AT row_sum(int row, const Pattern& P, const MT* __restrict__ val, F&& fetch) {
   // a wavefront covers exactly one slice, so the slice data are wave-uniform
   const int s = __builtin_amdgcn_readfirstlane(row >> 6);
-  const int beg = slice_ptr[s];
-  const int w = (slice_ptr[s + 1] - beg) >> 6;
+  const int beg = P.sp[s];
+  const int w = (P.sp[s + 1] - beg) >> 6;
   const int k0 = beg + (row & (kSlice - 1));
+  if (P.dia[s]) {
+    const int32_t* offs = P.doff + (size_t)s * kDiaMax;
+    switch (w) {
+      case 1: return row_sum_dia_w<1, AT>(row, k0, offs, P.nmax, val, fetch);
+      case 2: return row_sum_dia_w<2, AT>(row, k0, offs, P.nmax, val, fetch);
+      case 3: return row_sum_dia_w<3, AT>(row, k0, offs, P.nmax, val, fetch);
+      case 4: return row_sum_dia_w<4, AT>(row, k0, offs, P.nmax, val, fetch);
+      case 5: return row_sum_dia_w<5, AT>(row, k0, offs, P.nmax, val, fetch);
+      case 6: return row_sum_dia_w<6, AT>(row, k0, offs, P.nmax, val, fetch);
+      default: {
+        AT acc = 0;
+        for (int j = 0; j < w; ++j) {
+          const int cc = row + offs[j];
+          acc += ld<AT>(val[k0 + j * kSlice]) * fetch(cc < 0 ? 0 : (cc > P.nmax ? P.nmax : cc));
+        }
+        return acc;
+      }
+    }
+  }
+  const int32_t* __restrict__ col = P.col;
   switch (w) {
     case 0: return AT(0);
     case 1: return row_sum_w<1, AT>(k0, col, val, fetch);
@@ -112,8 +161,6 @@ __device__ __forceinline__ AT row_sum(int row, const int32_t* __restrict__ slice
     case 4: return row_sum_w<4, AT>(k0, col, val, fetch);
     case 5: return row_sum_w<5, AT>(k0, col, val, fetch);
     case 6: return row_sum_w<6, AT>(k0, col, val, fetch);
-    case 7: return row_sum_w<7, AT>(k0, col, val, fetch);
-    case 8: return row_sum_w<8, AT>(k0, col, val, fetch);
     default: {
       AT acc = 0;
       for (int j = 0; j < w; ++j) {

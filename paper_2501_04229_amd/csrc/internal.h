@@ -26,6 +26,8 @@ constexpr int kPadRows = kTile;
 constexpr int kMaxBlocks = 4096;
 // Stride between per-block arrival flags (one 64-byte line each).
 constexpr int kFlagStride = 8;
+// Largest number of distinct column offsets of a diagonal-style slice.
+constexpr int kDiaMax = 8;
 
 #define GADI_HIP_CHECK(expr)                                \
   do {                                                      \
@@ -59,8 +61,12 @@ struct DevInfo {
 //   Off-diagonal entries of the union pattern of A and A^T are packed as
 //   SELL-64: slice s covers rows [64 s, 64 s + 64); its entries start at
 //   slice_ptr[s]; slot j of row (64 s + l) is element slice_ptr[s] + 64 j + l.
-//   The slice width is (slice_ptr[s+1] - slice_ptr[s]) / 64.  Padding slots
-//   hold col = row and value 0.  Diagonals are stored densely.
+//   The slice width is (slice_ptr[s+1] - slice_ptr[s]) / 64.  In an explicit
+//   slice, padding slots hold col = row and value 0.  A diagonal-style slice
+//   (slice_dia[s] > 0) has one slot per column offset dia_off[s][j]: slot j of
+//   row i is the entry (i, i + dia_off[s][j]), value 0 where the row has no
+//   such entry; its column indices are implied and never read.  Diagonals are
+//   stored densely.
 struct System {
   int n = 0;       // rows
   int npad = 0;    // rows rounded up to a tile
@@ -72,6 +78,11 @@ struct System {
   int device = 0;
   hipStream_t stream = nullptr;
 
+  int64_t dia_slices = 0;
+  int64_t dia_slots = 0;         // slots of diagonal-style slices
+  int64_t explicit_entries = 0;  // structural entries in explicit slices
+  int32_t* slice_dia = nullptr;  // [nslices]: number of offsets of a diagonal-style slice, 0 = explicit
+  int32_t* dia_off = nullptr;    // [nslices * kDiaMax]: ascending column offsets col - row
   int32_t* slice_ptr = nullptr;  // [nslices + 1]
   int32_t* col = nullptr;        // [nslots]
   double* a_off = nullptr;       // [nslots] A values on the union pattern
@@ -97,6 +108,7 @@ struct System {
   double* part = nullptr;    // [2][kMaxBlocks][4]
   double* result = nullptr;  // [2][4]
   DevInfo* info = nullptr;
+  long long* prof = nullptr;  // [20] per-phase profile of the last solve
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // launch shape of the solve kernel per precision mode, chosen by the autotuner
   int tuned_block[3] = {0, 0, 0};

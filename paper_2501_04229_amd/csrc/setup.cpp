@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -63,9 +64,9 @@ static gadi_status upload(T** dst, const std::vector<T>& src) {
 }
 
 void free_system(System& s) {
-  void* ptrs[] = {s.slice_ptr, s.col,     s.a_off,   s.a_diag,  s.h_off64, s.s_off64, s.h_diag64,
+  void* ptrs[] = {s.slice_dia, s.dia_off, s.slice_ptr, s.col,     s.a_off,   s.a_diag,  s.h_off64, s.s_off64, s.h_diag64,
                   s.h_off16,   s.s_off16, s.h_diag16, s.h_off32, s.s_off32, s.h_diag32, s.ws,
-                  s.hist,      s.sync,    s.flags,   s.part,    s.result,  s.info};
+                  s.hist,      s.sync,    s.flags,   s.part,    s.result,  s.info, s.prof};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (s.ev0) (void)hipEventDestroy(s.ev0);
@@ -155,14 +156,42 @@ extern "C" gadi_status gadi_setup(const gadi_csr* A, gadi_splitting split, gadi_
 
   const int npad = (n + kPadRows - 1) / kPadRows * kPadRows;
   const int nslices = npad / kSlice;
-  std::vector<int32_t> width(nslices, 0);
+  // Per slice: the longest row (SELL width) and the distinct column offsets
+  // col - row of its off-diagonal entries.  A slice with at most kDiaMax
+  // distinct offsets is stored diagonal-style: one slot per offset (ascending),
+  // zero-valued phantom entries where a row lacks that offset, no per-entry
+  // column index.  Every slice of a stencil matrix qualifies.
+  std::vector<int32_t> width(nslices, 0), is_dia(nslices, 1), nofs(nslices, 0);
+  std::vector<int32_t> dia_off((size_t)nslices * kDiaMax, 0);
   int64_t nnz_off = 0;
   for (int i = 0; i < n; ++i) {
+    const int s = i / kSlice;
     int cnt = 0;
-    merge_row(i, [&](int c, double, double) { cnt += (c != i); });
+    int32_t* offs = &dia_off[(size_t)s * kDiaMax];
+    merge_row(i, [&](int c, double, double) {
+      if (c == i) return;
+      ++cnt;
+      if (!is_dia[s]) return;
+      const int32_t d = c - i;
+      int k = 0;
+      while (k < nofs[s] && offs[k] != d) ++k;
+      if (k == nofs[s]) {
+        if (nofs[s] == kDiaMax) is_dia[s] = 0;
+        else offs[nofs[s]++] = d;
+      }
+    });
     nnz_off += cnt;
-    int s = i / kSlice;
     if (cnt > width[s]) width[s] = cnt;
+  }
+  int64_t dia_slices = 0;
+  for (int s = 0; s < nslices; ++s) {
+    if (is_dia[s]) {
+      std::sort(dia_off.begin() + (size_t)s * kDiaMax, dia_off.begin() + (size_t)s * kDiaMax + nofs[s]);
+      width[s] = nofs[s];
+      ++dia_slices;
+    } else {
+      nofs[s] = 0;
+    }
   }
   std::vector<int32_t> slice_ptr(nslices + 1, 0);
   int64_t acc = 0;
@@ -189,16 +218,20 @@ extern "C" gadi_status gadi_setup(const gadi_csr* A, gadi_splitting split, gadi_
   } catch (const std::bad_alloc&) {
     return GADI_ENOMEM;
   }
-  // padding slots point at their own row (rows past n at row n - 1, so a
-  // product with a caller's length-n vector never reads past its end)
+  // Empty slots: in explicit slices they point at their own row (rows past n
+  // at row n - 1, so a product with a caller's length-n vector never reads
+  // past its end); in diagonal-style slices the kernels never read the column
+  // array, which marks phantom entries with -1.
   for (int s = 0; s < nslices; ++s)
     for (int j = 0; j < width[s]; ++j)
       for (int l = 0; l < kSlice; ++l) {
         const int row = s * kSlice + l;
-        hcol[slice_ptr[s] + (int64_t)j * kSlice + l] = row < n ? row : n - 1;
+        hcol[slice_ptr[s] + (int64_t)j * kSlice + l] = is_dia[s] ? -1 : (row < n ? row : n - 1);
       }
   for (int i = 0; i < n; ++i) {
-    int s = i / kSlice, l = i % kSlice, j = 0;
+    const int s = i / kSlice, l = i % kSlice;
+    const int32_t* offs = &dia_off[(size_t)s * kDiaMax];
+    int j = 0;
     merge_row(i, [&](int c, double va, double vt) {
       double hv = (va + vt) / 2.0, sv = (va - vt) / 2.0;
       if (c == i) {
@@ -207,14 +240,18 @@ extern "C" gadi_status gadi_setup(const gadi_csr* A, gadi_splitting split, gadi_
         hd16[i] = f64_to_f16_rne(hv);
         return;
       }
-      int64_t k = slice_ptr[s] + (int64_t)j * kSlice + l;
+      int slot = j++;
+      if (is_dia[s]) {
+        slot = 0;
+        while (offs[slot] != c - i) ++slot;
+      }
+      int64_t k = slice_ptr[s] + (int64_t)slot * kSlice + l;
       hcol[k] = c;
       a_off[k] = va;
       h64[k] = hv;
       s64[k] = sv;
       h16[k] = f64_to_f16_rne(hv);
       s16[k] = f64_to_f16_rne(sv);
-      ++j;
     });
   }
   // free the host CSR copies before allocating device memory
@@ -233,12 +270,28 @@ extern "C" gadi_status gadi_setup(const gadi_csr* A, gadi_splitting split, gadi_
   S.nnz_off = nnz_off;
   S.nslots = nslots;
   S.max_width = max_width;
+  S.dia_slices = dia_slices;
+  int64_t dslots = 0, expl = 0;
+  for (int sl = 0; sl < nslices; ++sl) {
+    const int64_t slots = (int64_t)(slice_ptr[sl + 1] - slice_ptr[sl]);
+    if (is_dia[sl]) dslots += slots;
+  }
+  for (int sl = 0; sl < nslices; ++sl) {
+    if (is_dia[sl]) continue;
+    for (int64_t k = slice_ptr[sl]; k < slice_ptr[sl + 1]; ++k) {
+      const int row = sl * kSlice + (int)((k - slice_ptr[sl]) % kSlice);
+      if (row < n && hcol[k] != row) ++expl;
+    }
+  }
+  S.dia_slots = dslots;
+  S.explicit_entries = expl;
   (void)hipGetDevice(&S.device);
   gadi_status st = GADI_OK;
   if ((st = upload(&S.slice_ptr, slice_ptr)) != GADI_OK || (st = upload(&S.col, hcol)) != GADI_OK ||
       (st = upload(&S.a_off, a_off)) != GADI_OK || (st = upload(&S.a_diag, a_diag)) != GADI_OK ||
       (st = upload(&S.h_off64, h64)) != GADI_OK || (st = upload(&S.s_off64, s64)) != GADI_OK ||
-      (st = upload(&S.h_diag64, h_diag64)) != GADI_OK ||
+      (st = upload(&S.h_diag64, h_diag64)) != GADI_OK || (st = upload(&S.slice_dia, nofs)) != GADI_OK ||
+      (st = upload(&S.dia_off, dia_off)) != GADI_OK ||
       (st = upload((uint16_t**)&S.h_off16, h16)) != GADI_OK ||
       (st = upload((uint16_t**)&S.s_off16, s16)) != GADI_OK ||
       (st = upload((uint16_t**)&S.h_diag16, hd16)) != GADI_OK) {
@@ -290,6 +343,18 @@ extern "C" void gadi_default_options(gadi_options* o, gadi_precision prec) {
   o->grid_per_system = 0;
 }
 
+extern "C" gadi_status gadi_get_layout(gadi_handle* h, int64_t* out) {
+  if (!h || !out) return GADI_EINVAL;
+  const System& S = h->sys;
+  out[0] = S.n;
+  out[1] = S.npad;
+  out[2] = S.nnz_off;
+  out[3] = S.nslots;
+  out[4] = S.dia_slots;
+  out[5] = S.explicit_entries;
+  return GADI_OK;
+}
+
 extern "C" gadi_status gadi_get_split_fp16(gadi_handle* h, int32_t which, int32_t* out_rp, int32_t* out_col,
                                            uint16_t* out_val, int64_t* nnz_out) {
   if (!h || (which != 1 && which != 2)) return GADI_EINVAL;
@@ -316,7 +381,7 @@ extern "C" gadi_status gadi_get_split_fp16(gadi_handle* h, int32_t which, int32_
       uint16_t vj = 0;
       if (j < w) {
         int64_t k = sp[s] + (int64_t)j * kSlice + l;
-        if (c[k] == i) continue;  // padding
+        if (c[k] == i || c[k] < 0) continue;  // padding or phantom
         cj = c[k];
         vj = v[k];
       }

@@ -29,9 +29,10 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(SolveArgs a) {
   }
 }
 
-__global__ void reset_sync_kernel(SyncState* s, unsigned long long* flags, DevInfo* info) {
+__global__ void reset_sync_kernel(SyncState* s, unsigned long long* flags, DevInfo* info, long long* prof) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kMaxBlocks * kFlagStride; i += gridDim.x * blockDim.x)
     flags[i] = 0ull;
+  if (prof && blockIdx.x == 0 && threadIdx.x < 20) prof[threadIdx.x] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     s->arrive = 0ull;
     s->release = 0ull;
@@ -90,6 +91,8 @@ gadi_status ensure_workspace(System& s) {
   GADI_HIP_CHECK(hipMalloc((void**)&s.flags, sizeof(unsigned long long) * kMaxBlocks * kFlagStride));
   GADI_HIP_CHECK(hipMalloc((void**)&s.result, sizeof(double) * 8));
   GADI_HIP_CHECK(hipMalloc((void**)&s.info, sizeof(DevInfo)));
+  GADI_HIP_CHECK(hipMalloc((void**)&s.prof, sizeof(long long) * 20));
+  GADI_HIP_CHECK(hipMemset(s.prof, 0, sizeof(long long) * 20));
   GADI_HIP_CHECK(hipEventCreate(&s.ev0));
   GADI_HIP_CHECK(hipEventCreate(&s.ev1));
   return GADI_OK;
@@ -127,7 +130,7 @@ static gadi_status launch_t(System& s, SolveArgs a, int per_cu) {
   if (G > kMaxBlocks) G = kMaxBlocks;
   if (G < 1) G = 1;
   a.ntiles = ntiles;
-  hipLaunchKernelGGL(reset_sync_kernel, dim3(32), dim3(1024), 0, s.stream, s.sync, s.flags, s.info);
+  hipLaunchKernelGGL(reset_sync_kernel, dim3(32), dim3(1024), 0, s.stream, s.sync, s.flags, s.info, a.prof);
   GADI_HIP_CHECK(hipGetLastError());
   void* kargs[] = {(void*)&a};
   GADI_HIP_CHECK(hipLaunchCooperativeKernel((const void*)solve_kernel<Mode, BLOCK, FUSED>, dim3((unsigned)G), dim3(BLOCK),
@@ -177,8 +180,8 @@ static gadi_status tune_solve(System& s, int prec, SolveArgs a, double* dx) {
     return GADI_OK;
   }
   // {threads per block, blocks per CU, fused inner solves}
-  static const int cand[][3] = {{1024, 1, 0}, {512, 2, 0}, {512, 1, 0}, {256, 4, 0}, {256, 2, 0},
-                                {1024, 1, 1}, {512, 2, 1}, {512, 1, 1}, {256, 4, 1}, {256, 2, 1}};
+  static const int cand[][3] = {{1024, 1, 0}, {1024, 2, 0}, {512, 4, 0}, {512, 2, 0}, {512, 1, 0}, {256, 4, 0},
+                                {256, 2, 0}, {1024, 1, 1}, {1024, 2, 1}, {512, 4, 1}, {512, 2, 1}, {256, 4, 1}};
   a.maxit_out = a.maxit_out < 3 ? a.maxit_out : 3;
   a.hist = nullptr;
   a.hist_cap = 0;
@@ -279,6 +282,8 @@ extern "C" gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x,
   a.hist_cap = o.record_history ? s.hist_cap : 0;
   a.slice_ptr = s.slice_ptr;
   a.col = s.col;
+  a.slice_dia = s.slice_dia;
+  a.dia_off = s.dia_off;
   a.a_off = s.a_off;
   a.a_diag = s.a_diag;
   a.b = db;
@@ -299,6 +304,7 @@ extern "C" gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x,
   a.info = s.info;
   a.hist = o.record_history ? s.hist : nullptr;
   a.timeout = barrier_timeout_ticks();
+  a.prof = s.prof;
   if (o.prec == GADI_PREC_FP16_IR) {
     a.h_off = s.h_off16;
     a.s_off = s.s_off16;
@@ -347,6 +353,17 @@ extern "C" int32_t gadi_get_history(gadi_handle* h, double* out, int32_t cap) {
   if (n <= 0) return 0;
   if (hipMemcpy(out, h->sys.hist, sizeof(double) * n, hipMemcpyDeviceToHost) != hipSuccess) return 0;
   return n;
+}
+
+extern "C" gadi_status gadi_get_phase_profile(gadi_handle* h, double* seconds, int64_t* counts) {
+  if (!h || !seconds || !counts || !h->sys.prof) return GADI_EINVAL;
+  long long buf[20];
+  GADI_HIP_CHECK(hipMemcpy(buf, h->sys.prof, sizeof(buf), hipMemcpyDeviceToHost));
+  for (int i = 0; i < 10; ++i) {
+    seconds[i] = (double)buf[i] / ((double)g_wall_rate_khz * 1000.0);
+    counts[i] = buf[10 + i];
+  }
+  return GADI_OK;
 }
 
 extern "C" int32_t gadi_solver_blocks(gadi_handle* h, int32_t* threads) {

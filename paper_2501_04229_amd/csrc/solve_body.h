@@ -30,6 +30,8 @@ struct SolveArgs {
   int n, npad, ntiles, maxit_out, maxit_in, hist_cap;
   const int32_t* slice_ptr;
   const int32_t* col;
+  const int32_t* slice_dia;
+  const int32_t* dia_off;
   const double* a_off;
   const double* a_diag;
   const void* h_off;
@@ -52,6 +54,8 @@ struct SolveArgs {
   // Batched sweeps only: best work (operator products) of a converged trial
   // of this system so far; a trial stops (EMAXIT) once its own work exceeds it.
   unsigned long long* prune;
+  // optional per-phase profile of block 0: wall-clock ticks [10], phase counts [10]
+  long long* prof;
 };
 
 // Reduction into out[4] under the caller's synchronisation policy; leaves the
@@ -126,6 +130,19 @@ struct BlockRed {
   }
 };
 
+// The same, charging the block-0 time since the previous reduction to phase
+// `id` of the optional per-phase profile (a.prof: ticks[10], counts[10]).
+#define ALLREDUCE_P(id, a0, a1, a2, a3)                                    \
+  do {                                                                     \
+    if (a.prof && blockIdx.x == 0 && threadIdx.x == 0) {                   \
+      const long long now_ = wall_clock64();                               \
+      a.prof[(id)] += now_ - t_mark;                                       \
+      a.prof[10 + (id)] += 1;                                              \
+    }                                                                      \
+    ALLREDUCE(a0, a1, a2, a3);                                             \
+    if (a.prof && blockIdx.x == 0 && threadIdx.x == 0) t_mark = wall_clock64(); \
+  } while (0)
+
 static __device__ __forceinline__ int clamp_exp(int e) { return e < -120 ? -120 : (e > 120 ? 120 : e); }
 
 // The refinement loop of Algorithm 1 for rows [t0 * BLOCK, t1 * BLOCK) of one
@@ -168,8 +185,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
 
   const int tid = threadIdx.x;
 
-  const int32_t* __restrict__ sp = a.slice_ptr;
-  const int32_t* __restrict__ col = a.col;
+  const Pattern pat{a.slice_ptr, a.col, a.slice_dia, a.dia_off, a.n - 1};
   const MT* __restrict__ hoff = (const MT*)a.h_off;
   const MT* __restrict__ soff = (const MT*)a.s_off;
   const MT* __restrict__ hdiag = (const MT*)a.h_diag;
@@ -195,6 +211,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
   auto rnd = [](AT v) { return ld<AT>(st<VT>(v)); };
 
   double out[4];
+  long long t_mark = (a.prof && blockIdx.x == 0 && threadIdx.x == 0) ? wall_clock64() : 0;
   double rho0 = 0.0, res = 0.0;
   int status = GADI_EMAXIT;
   int sweep = 0;
@@ -207,13 +224,13 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
       for (int t = t0; t < t1; ++t) {
         const int row = t * BLOCK + tid;
         const double ax = a.a_diag[row] * x[row] +
-                          row_sum<double>(row, sp, col, a.a_off, [&](int c) { return x[c]; });
+                          row_sum<double>(row, pat, a.a_off, [&](int c) { return x[c]; });
         const double ri = b[row] - ax;
         r[row] = (RT)ri;
         s0 += ri * ri;
         m3 = fmax(m3, fabs(ri));
       }
-      ALLREDUCE(s0, 0.0, 0.0, m3);
+      ALLREDUCE_P(0, s0, 0.0, 0.0, m3);
     }
     const double rho = sqrt(out[0]);
     const double rmax = out[3];
@@ -255,14 +272,14 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
           const int row = t * BLOCK + tid;
           const AT ri = rnd((AT)r[row] * sc1);
           const AT kr = (alpha + ld<AT>(hdiag[row])) * ri +
-                        row_sum<AT>(row, sp, col, hoff, [&](int c) { return rnd((AT)r[c] * sc1); });
+                        row_sum<AT>(row, pat, hoff, [&](int c) { return rnd((AT)r[c] * sc1); });
           const AT wi = rnd(kr);
           R[0][row] = st<VT>(ri);
           W[0][row] = st<VT>(wi);
           g0 += (double)ri * (double)ri;
           d0 += (double)wi * (double)ri;
         }
-        ALLREDUCE(g0, d0, 0.0, 0.0);
+        ALLREDUCE_P(1, g0, d0, 0.0, 0.0);
       }
       double gam = out[0], del = out[1];
       const double gam0 = gam;
@@ -296,7 +313,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
             const AT pi = k == 0 ? ri : rnd(fma_at<AT>(bkt, ld<AT>(P[row]), ri));
             const ST zi = (k == 0 ? ST(0) : z[row]) + (ST)(akt * pi);
             const AT rn = rnd(fma_at<AT>(-akt, si, ri));
-            const AT kr = (alpha + ld<AT>(hdiag[row])) * rn + row_sum<AT>(row, sp, col, hoff, r_next);
+            const AT kr = (alpha + ld<AT>(hdiag[row])) * rn + row_sum<AT>(row, pat, hoff, r_next);
             const AT wn = rnd(kr);
             snew[row] = st<VT>(si);
             P[row] = st<VT>(pi);
@@ -307,7 +324,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
             d1 += (double)wn * (double)rn;
             m3 = fmax(m3, fabs((double)zi));
           }
-          ALLREDUCE(g1, d1, 0.0, m3);
+          ALLREDUCE_P(2, g1, d1, 0.0, m3);
           gam_prev = gam;
           a_prev = ak;
           gam = out[0];
@@ -329,7 +346,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
           const VT pi = st<VT>((AT)r[row] * sc1);
           const AT api = ld<AT>(pi);
           const AT kp = (alpha + ld<AT>(hdiag[row])) * api +
-                        row_sum<AT>(row, sp, col, hoff, [&](int c) { return ld<AT>(st<VT>((AT)r[c] * sc1)); });
+                        row_sum<AT>(row, pat, hoff, [&](int c) { return ld<AT>(st<VT>((AT)r[c] * sc1)); });
           const VT qi = st<VT>(kp);
           vr[row] = pi;
           vp[row] = pi;
@@ -337,7 +354,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
           s0 += (double)api * (double)ld<AT>(qi);
           s1 += (double)api * (double)api;
         }
-        ALLREDUCE(s0, s1, 0.0, 0.0);
+        ALLREDUCE_P(1, s0, s1, 0.0, 0.0);
         pq = out[0];
         rr0 = out[1];
         rr = rr0;
@@ -361,7 +378,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
             s0 += dr * dr;
             m3 = fmax(m3, fabs((double)zi));
           }
-          ALLREDUCE(s0, 0.0, 0.0, m3);
+          ALLREDUCE_P(3, s0, 0.0, 0.0, m3);
           const double rr_new = out[0];
           zmax = out[3];
           ++it;
@@ -373,14 +390,14 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
             const int row = t * BLOCK + tid;
             const AT ri = ld<AT>(vr[row]);
             const AT kr = (alpha + ld<AT>(hdiag[row])) * ri +
-                          row_sum<AT>(row, sp, col, hoff, [&](int c) { return ld<AT>(vr[c]); });
+                          row_sum<AT>(row, pat, hoff, [&](int c) { return ld<AT>(vr[c]); });
             const VT pn = st<VT>(ri + beta * ld<AT>(vp[row]));
             const VT qn = st<VT>(kr + beta * ld<AT>(vq[row]));
             vp[row] = pn;
             vq[row] = qn;
             s0 += (double)ld<AT>(pn) * (double)ld<AT>(qn);
           }
-          ALLREDUCE(s0, 0.0, 0.0, 0.0);
+          ALLREDUCE_P(2, s0, 0.0, 0.0, 0.0);
           pq = out[0];
         }
       }
@@ -407,12 +424,12 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
           for (int t = t0; t < t1; ++t) {
             const int row = t * BLOCK + tid;
             const AT gi = g_at(row);
-            const AT tv = inv_alpha * row_sum<AT>(row, sp, col, soff, g_at);
+            const AT tv = inv_alpha * row_sum<AT>(row, pat, soff, g_at);
             R[0][row] = st<VT>(gi);
             T[row] = st<VT>(tv);
             g0 += (double)gi * (double)gi;
           }
-          ALLREDUCE(g0, 0.0, 0.0, 0.0);
+          ALLREDUCE_P(4, g0, 0.0, 0.0, 0.0);
         }
         const double gs0 = out[0];
         // w_0 = r_0 - (S/alpha) t
@@ -421,11 +438,11 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
           for (int t = t0; t < t1; ++t) {
             const int row = t * BLOCK + tid;
             const AT ri = ld<AT>(R[0][row]);
-            const AT wi = rnd(ri - inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) { return ld<AT>(T[c]); }));
+            const AT wi = rnd(ri - inv_alpha * row_sum<AT>(row, pat, soff, [&](int c) { return ld<AT>(T[c]); }));
             W[0][row] = st<VT>(wi);
             d0 += (double)wi * (double)ri;
           }
-          ALLREDUCE(0.0, d0, 0.0, 0.0);
+          ALLREDUCE_P(4, 0.0, d0, 0.0, 0.0);
         }
         double gam = gs0, del = out[1];
         if (gs0 > 0.0) {
@@ -458,14 +475,14 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
               const AT pi = k == 0 ? ri : rnd(fma_at<AT>(bkt, ld<AT>(P[row]), ri));
               wsol[row] = (k == 0 ? ST(0) : wsol[row]) + (ST)(akt * pi);
               const AT rn = rnd(fma_at<AT>(-akt, si, ri));
-              const AT tv = inv_alpha * row_sum<AT>(row, sp, col, soff, r_next);
+              const AT tv = inv_alpha * row_sum<AT>(row, pat, soff, r_next);
               snew[row] = st<VT>(si);
               P[row] = st<VT>(pi);
               rnew[row] = st<VT>(rn);
               T[row] = st<VT>(tv);
               g1 += (double)rn * (double)rn;
             }
-            ALLREDUCE(g1, 0.0, 0.0, 0.0);
+            ALLREDUCE_P(5, g1, 0.0, 0.0, 0.0);
             gam_prev = gam;
             a_prev = ak;
             gam = out[0];
@@ -476,11 +493,11 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
             for (int t = t0; t < t1; ++t) {
               const int row = t * BLOCK + tid;
               const AT rn = ld<AT>(rnew[row]);
-              const AT wn = rnd(rn - inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) { return ld<AT>(T[c]); }));
+              const AT wn = rnd(rn - inv_alpha * row_sum<AT>(row, pat, soff, [&](int c) { return ld<AT>(T[c]); }));
               wnew[row] = st<VT>(wn);
               d1 += (double)wn * (double)rn;
             }
-            ALLREDUCE(0.0, d1, 0.0, 0.0);
+            ALLREDUCE_P(6, 0.0, d1, 0.0, 0.0);
             del = out[1];
           }
         }
@@ -496,7 +513,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
           for (int t = t0; t < t1; ++t) {
             const int row = t * BLOCK + tid;
             const VT gi = st<VT>(two_m_omega * (AT)z[row] * sc2);
-            const AT tv = inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) {
+            const AT tv = inv_alpha * row_sum<AT>(row, pat, soff, [&](int c) {
                             return ld<AT>(st<VT>(two_m_omega * (AT)z[c] * sc2));
                           });
             vr[row] = gi;
@@ -505,7 +522,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
             const double dg = (double)ld<AT>(gi);
             s1 += dg * dg;
           }
-          ALLREDUCE(0.0, s1, 0.0, 0.0);
+          ALLREDUCE_P(4, 0.0, s1, 0.0, 0.0);
           rrs0 = out[1];
         }
         double rrs = rrs0;
@@ -516,12 +533,12 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
             for (int t = t0; t < t1; ++t) {
               const int row = t * BLOCK + tid;
               const AT pi = ld<AT>(vp[row]);
-              const AT qv = pi - inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) { return ld<AT>(vt[c]); });
+              const AT qv = pi - inv_alpha * row_sum<AT>(row, pat, soff, [&](int c) { return ld<AT>(vt[c]); });
               const VT qi = st<VT>(qv);
               vq[row] = qi;
               s0 += (double)pi * (double)ld<AT>(qi);
             }
-            ALLREDUCE(s0, 0.0, 0.0, 0.0);
+            ALLREDUCE_P(6, s0, 0.0, 0.0, 0.0);
             const double pqs = out[0];
             if (!(pqs > 0.0) || !isfinite(pqs)) {
               if (its == 0) status = isfinite(pqs) ? GADI_ENOTSPD : (Mode::id == GADI_PREC_FP16_IR ? GADI_EOVERFLOW16 : GADI_EDIVERGED);
@@ -538,7 +555,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
               const double dr = (double)ld<AT>(ri);
               s0 += dr * dr;
             }
-            ALLREDUCE(s0, 0.0, 0.0, 0.0);
+            ALLREDUCE_P(7, s0, 0.0, 0.0, 0.0);
             const double rr_new = out[0];
             ++its;
             if (rr_new <= eps_s2 * rrs0 || its >= a.maxit_in || !isfinite(rr_new)) break;
@@ -547,11 +564,11 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
             for (int t = t0; t < t1; ++t) {
               const int row = t * BLOCK + tid;
               const AT ri = ld<AT>(vr[row]);
-              const AT sr = inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) { return ld<AT>(vr[c]); });
+              const AT sr = inv_alpha * row_sum<AT>(row, pat, soff, [&](int c) { return ld<AT>(vr[c]); });
               vt[row] = st<VT>(sr + beta * ld<AT>(vt[row]));
               vp[row] = st<VT>(ri + beta * ld<AT>(vp[row]));
             }
-            ALLREDUCE(0.0, 0.0, 0.0, 0.0);
+            ALLREDUCE_P(5, 0.0, 0.0, 0.0, 0.0);
           }
         }
       }
@@ -563,10 +580,10 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
         const double unscale = ldexp(1.0, e1 + e2);
         for (int t = t0; t < t1; ++t) {
           const int row = t * BLOCK + tid;
-          const AT ui = (AT)wsol[row] - inv_alpha * row_sum<AT>(row, sp, col, soff, [&](int c) { return (AT)wsol[c]; });
+          const AT ui = (AT)wsol[row] - inv_alpha * row_sum<AT>(row, pat, soff, [&](int c) { return (AT)wsol[c]; });
           x[row] += (double)ui * unscale;
         }
-        ALLREDUCE(0.0, 0.0, 0.0, 0.0);
+        ALLREDUCE_P(8, 0.0, 0.0, 0.0, 0.0);
       }
     }
     ++sweep;

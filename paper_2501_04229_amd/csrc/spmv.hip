@@ -9,37 +9,41 @@ namespace gadi {
 
 // y = A x in double (the residual's operator, step 1 of Algorithm 1)
 __global__ void __launch_bounds__(kRowBlock) spmv_a64_kernel(const int32_t* __restrict__ sp, const int32_t* __restrict__ col,
+    const int32_t* __restrict__ dia, const int32_t* __restrict__ doff,
                                                            const double* __restrict__ off, const double* __restrict__ diag,
                                                            const double* __restrict__ x, double* __restrict__ y, int n) {
   const int row = blockIdx.x * kRowBlock + threadIdx.x;
   const double xi = row < n ? x[row] : 0.0;
-  const double acc = diag[row] * xi + row_sum<double>(row, sp, col, off, [&](int c) { return x[c]; });
+  const double acc = diag[row] * xi + row_sum<double>(row, Pattern{sp, col, dia, doff, n - 1}, off, [&](int c) { return x[c]; });
   if (row < n) y[row] = acc;
 }
 
 // y = (alpha I + H) x with H, x, y in the value type MT, arithmetic in AT
 template <class MT, class AT>
 __global__ void __launch_bounds__(kRowBlock) spmv_h_kernel(const int32_t* __restrict__ sp, const int32_t* __restrict__ col,
+    const int32_t* __restrict__ dia, const int32_t* __restrict__ doff,
                                                          const MT* __restrict__ off, const MT* __restrict__ diag,
                                                          const MT* __restrict__ x, MT* __restrict__ y, AT alpha, int n) {
   const int row = blockIdx.x * kRowBlock + threadIdx.x;
   const AT xi = row < n ? ld<AT>(x[row]) : AT(0);
-  const AT acc = (alpha + ld<AT>(diag[row])) * xi + row_sum<AT>(row, sp, col, off, [&](int c) { return ld<AT>(x[c]); });
+  const AT acc = (alpha + ld<AT>(diag[row])) * xi + row_sum<AT>(row, Pattern{sp, col, dia, doff, n - 1}, off, [&](int c) { return ld<AT>(x[c]); });
   if (row < n) y[row] = st<MT>(acc);
 }
 
 // y = (I + S / alpha) x, half in/out, float arithmetic
 __global__ void __launch_bounds__(kRowBlock) spmv_s16_kernel(const int32_t* __restrict__ sp, const int32_t* __restrict__ col,
+    const int32_t* __restrict__ dia, const int32_t* __restrict__ doff,
                                                            const __half* __restrict__ off, const __half* __restrict__ x,
                                                            __half* __restrict__ y, float inv_alpha, int n) {
   const int row = blockIdx.x * kRowBlock + threadIdx.x;
   const float xi = row < n ? __half2float(x[row]) : 0.f;
-  const float acc = xi + inv_alpha * row_sum<float>(row, sp, col, off, [&](int c) { return __half2float(x[c]); });
+  const float acc = xi + inv_alpha * row_sum<float>(row, Pattern{sp, col, dia, doff, n - 1}, off, [&](int c) { return __half2float(x[c]); });
   if (row < n) y[row] = __float2half_rn(acc);
 }
 
 // Per-block Gershgorin extrema: [min(H_ii - R^H_i), max(H_ii + R^H_i), max R^S_i, min R^S_i]
 __global__ void __launch_bounds__(kRowBlock) gershgorin_kernel(const int32_t* __restrict__ sp, const int32_t* __restrict__ col,
+    const int32_t* __restrict__ dia, const int32_t* __restrict__ doff,
                                                              const double* __restrict__ hoff, const double* __restrict__ soff,
                                                              const double* __restrict__ hdiag, int n, double* __restrict__ out) {
   __shared__ double sh[4][4];
@@ -92,19 +96,19 @@ extern "C" gadi_status gadi_spmv(gadi_handle* h, int32_t which, double alpha, co
   const dim3 grid(s.npad / kRowBlock), block(kRowBlock);
   switch (which) {
     case 0:
-      hipLaunchKernelGGL(spmv_a64_kernel, grid, block, 0, s.stream, s.slice_ptr, s.col, s.a_off, s.a_diag,
+      hipLaunchKernelGGL(spmv_a64_kernel, grid, block, 0, s.stream, s.slice_ptr, s.col, s.slice_dia, s.dia_off, s.a_off, s.a_diag,
                          (const double*)x, (double*)y, s.n);
       break;
     case 1:
-      hipLaunchKernelGGL((spmv_h_kernel<__half, float>), grid, block, 0, s.stream, s.slice_ptr, s.col, s.h_off16,
+      hipLaunchKernelGGL((spmv_h_kernel<__half, float>), grid, block, 0, s.stream, s.slice_ptr, s.col, s.slice_dia, s.dia_off, s.h_off16,
                          s.h_diag16, (const __half*)x, (__half*)y, (float)alpha, s.n);
       break;
     case 2:
-      hipLaunchKernelGGL(spmv_s16_kernel, grid, block, 0, s.stream, s.slice_ptr, s.col, s.s_off16, (const __half*)x,
+      hipLaunchKernelGGL(spmv_s16_kernel, grid, block, 0, s.stream, s.slice_ptr, s.col, s.slice_dia, s.dia_off, s.s_off16, (const __half*)x,
                          (__half*)y, (float)(1.0 / alpha), s.n);
       break;
     case 3:
-      hipLaunchKernelGGL((spmv_h_kernel<double, double>), grid, block, 0, s.stream, s.slice_ptr, s.col, s.h_off64,
+      hipLaunchKernelGGL((spmv_h_kernel<double, double>), grid, block, 0, s.stream, s.slice_ptr, s.col, s.slice_dia, s.dia_off, s.h_off64,
                          s.h_diag64, (const double*)x, (double*)y, alpha, s.n);
       break;
   }
@@ -119,7 +123,7 @@ extern "C" gadi_status gadi_features(gadi_handle* h, int32_t dim, int32_t grid, 
   const int nb = s.npad / kRowBlock;
   double* dpart = nullptr;
   GADI_HIP_CHECK(hipMalloc((void**)&dpart, sizeof(double) * 4 * nb));
-  hipLaunchKernelGGL(gershgorin_kernel, dim3(nb), dim3(kRowBlock), 0, s.stream, s.slice_ptr, s.col, s.h_off64, s.s_off64,
+  hipLaunchKernelGGL(gershgorin_kernel, dim3(nb), dim3(kRowBlock), 0, s.stream, s.slice_ptr, s.col, s.slice_dia, s.dia_off, s.h_off64, s.s_off64,
                      s.h_diag64, s.n, dpart);
   hipError_t e = hipGetLastError();
   std::vector<double> part((size_t)4 * nb);

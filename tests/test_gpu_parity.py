@@ -30,6 +30,9 @@ CASES = [
     ("3d17_b", lambda: gi.convdiff(17, 3, (3.0, 40.0, 0.5))),  # 4913 rows: ragged last tile
     ("2d7_b2", lambda: gi.convdiff(7, 2, 2.0)),                 # 49 rows: less than one slice
     ("3d40_b20", lambda: gi.convdiff(40, 3, 20.0)),
+    # irregular patterns: every slice stored with explicit columns / a mix of both layouts
+    ("2d40_rand", lambda: gi.convdiff_skew_perturbed(40, 2, 5.0, 3.0, 0.2, seed=3)),
+    ("3d12_mixed", lambda: gi.convdiff_skew_perturbed(12, 3, 8.0, 2.0, 0.2, seed=4, rows_fraction=0.02)),
 ]
 
 
