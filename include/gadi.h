@@ -105,7 +105,8 @@ void gadi_default_options(gadi_options* o, gadi_precision prec);
 
 /* Validate A, form H and S (Section 4.1 splitting) on the union pattern of A and
  * A^T, pack A, H, S into the device layout and return a handle.  EINVAL on a
- * malformed CSR or unsupported splitting; ENOMEM / EHIP on allocation failure.
+ * malformed CSR, n above 2^29 - 1024, more than 2^31 - 1 stored entries or an
+ * unsupported splitting; ENOMEM / EHIP on allocation failure.
  * The handle owns all device memory it allocates. */
 gadi_status gadi_setup(const gadi_csr* A, gadi_splitting split, gadi_handle** out);
 
@@ -208,10 +209,12 @@ const char* gadi_status_str(gadi_status s);
  * 6 CGNE second product, 7 CGNE update, 8 solution update, 9 unused. */
 gadi_status gadi_get_phase_profile(gadi_handle* h, double* seconds, int64_t* counts);
 
-/* Device layout of the packed matrices, out[6] = {n, padded rows, off-diagonal
+/* Device layout of the packed matrices, out[7] = {n, padded rows, off-diagonal
  * entries of the union pattern of A and A^T, stored slots (entries plus
  * padding / phantom zeros), stored slots in diagonal-style slices (no column
- * index stored), structural entries in explicit slices (int32 column each)}. */
+ * index stored), structural entries in explicit slices (int32 column each),
+ * offsets per slice when every slice is diagonal-style with the same offsets
+ * (4 or 6; 0 otherwise)}. */
 gadi_status gadi_get_layout(gadi_handle* h, int64_t* out);
 
 /* Launch shape of the last gadi_ir_solve on this handle: returns the number of

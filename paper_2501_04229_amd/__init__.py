@@ -227,10 +227,13 @@ class System:
         return {k: (sec[i], cnt[i]) for i, k in enumerate(self.PHASES)}
 
     def layout(self):
-        """Packed layout counts: dict with n, npad, nnz_off, slots, dia_slots, explicit_entries."""
-        out = (ctypes.c_int64 * 6)()
+        """Packed layout counts: dict with n, npad, nnz_off, slots, dia_slots,
+        explicit_entries, uniform_offsets (offsets per slice of a uniformly
+        diagonal-style layout, 0 if per-slice metadata is used)."""
+        out = (ctypes.c_int64 * 7)()
         _check(_lib.gadi_get_layout(self._h, out), "gadi_get_layout")
-        return dict(zip(("n", "npad", "nnz_off", "slots", "dia_slots", "explicit_entries"), list(out)))
+        return dict(zip(("n", "npad", "nnz_off", "slots", "dia_slots", "explicit_entries", "uniform_offsets"),
+                        list(out)))
 
     def features(self, dim, grid, beta):
         beta = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, dtype=np.float64), (dim,)))

@@ -107,7 +107,8 @@ __global__ void __launch_bounds__(BLOCK) batched_kernel(BatchArgs ba) {
     const long long t_start = wall_clock64();
     BlockRed<BLOCK> red;
     DevInfo r{};
-    (void)solve_body<Mode, BLOCK, false>(a, red, 0, S.npad / BLOCK, r);
+    const PatGeneric pat{Pattern{a.slice_ptr, a.col, a.slice_dia, a.dia_off, a.n - 1}};
+    (void)solve_body<Mode, BLOCK, false, 1>(a, red, pat, 0, S.npad / BLOCK, r);
     if (threadIdx.x == 0) {
       r.barriers = red.barriers;
       r.barrier_ticks = wall_clock64() - t_start;  // the unit's wall-clock ticks

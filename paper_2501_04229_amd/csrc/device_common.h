@@ -18,6 +18,7 @@ struct ModeF16 {
   using RT = float;
   using AT = float;
   static constexpr int id = GADI_PREC_FP16_IR;
+  static constexpr int tiles = 2;  // tiles per thread with loads in flight together
 };
 struct ModeF32 {
   using MT = float;
@@ -26,6 +27,7 @@ struct ModeF32 {
   using RT = float;
   using AT = float;
   static constexpr int id = GADI_PREC_FP32_IR;
+  static constexpr int tiles = 2;  // tiles per thread with loads in flight together
 };
 struct ModeF64 {
   using MT = double;
@@ -34,6 +36,7 @@ struct ModeF64 {
   using RT = double;
   using AT = double;
   static constexpr int id = GADI_PREC_FP64;
+  static constexpr int tiles = 1;  // tiles per thread with loads in flight together
 };
 
 template <class AT>

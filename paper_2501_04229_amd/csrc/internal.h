@@ -28,6 +28,8 @@ constexpr int kMaxBlocks = 4096;
 constexpr int kFlagStride = 8;
 // Largest number of distinct column offsets of a diagonal-style slice.
 constexpr int kDiaMax = 8;
+// largest system: its padded double vectors stay below 4 GiB
+constexpr int kMaxRows = (1 << 29) - kPadRows;
 
 #define GADI_HIP_CHECK(expr)                                \
   do {                                                      \
@@ -83,6 +85,9 @@ struct System {
   int64_t explicit_entries = 0;  // structural entries in explicit slices
   int32_t* slice_dia = nullptr;  // [nslices]: number of offsets of a diagonal-style slice, 0 = explicit
   int32_t* dia_off = nullptr;    // [nslices * kDiaMax]: ascending column offsets col - row
+  // > 0: every slice is diagonal-style with these same dia_uniform offsets
+  int dia_uniform = 0;
+  int32_t dia_u[kDiaMax] = {0, 0, 0, 0, 0, 0, 0, 0};
   int32_t* slice_ptr = nullptr;  // [nslices + 1]
   int32_t* col = nullptr;        // [nslots]
   double* a_off = nullptr;       // [nslots] A values on the union pattern

@@ -84,7 +84,9 @@ extern "C" gadi_status gadi_setup(const gadi_csr* A, gadi_splitting split, gadi_
   if (!A || split != GADI_SPLIT_HSS) return GADI_EINVAL;
   const int n = A->n;
   const int64_t nnz = A->nnz;
-  if (n < 1 || nnz < 0 || nnz >= (int64_t(1) << 31) || !A->row_ptr || (nnz > 0 && (!A->col_idx || !A->val)))
+  // n <= kMaxRows: every solver vector of doubles stays below 4 GiB (32-bit byte offsets)
+  if (n < 1 || n > kMaxRows || nnz < 0 || nnz >= (int64_t(1) << 31) || !A->row_ptr ||
+      (nnz > 0 && (!A->col_idx || !A->val)))
     return GADI_EINVAL;
 
   std::vector<int32_t> rp(n + 1), col;
@@ -193,6 +195,42 @@ extern "C" gadi_status gadi_setup(const gadi_csr* A, gadi_splitting split, gadi_
       nofs[s] = 0;
     }
   }
+  // Uniform diagonal-style layout: if every slice is diagonal-style and the
+  // union of their offsets has 4 or 6 members (the 2-D and 3-D stencils), every
+  // slice is stored with the union's offsets, phantom zeros where a slice
+  // lacks one, as long as that adds at most a quarter to the stored slots of
+  // the slices that hold rows.
+  // The solver then takes the offsets from its arguments instead of reading
+  // per-slice metadata.
+  int dia_uniform = 0;
+  std::vector<int32_t> uni;
+  if (dia_slices == nslices) {
+    int64_t slots_before = 0;
+    for (int s = 0; s < nslices; ++s) {
+      slots_before += (int64_t)width[s] * kSlice;
+      for (int k = 0; k < nofs[s]; ++k) uni.push_back(dia_off[(size_t)s * kDiaMax + k]);
+      if (uni.size() > 64) {  // keep the candidate set small while scanning
+        std::sort(uni.begin(), uni.end());
+        uni.erase(std::unique(uni.begin(), uni.end()), uni.end());
+        if (uni.size() > (size_t)kDiaMax) break;
+      }
+    }
+    std::sort(uni.begin(), uni.end());
+    uni.erase(std::unique(uni.begin(), uni.end()), uni.end());
+    // trailing slices past row n - 1 (tile padding) hold no rows: not counted
+    const int64_t used_slices = (n + kSlice - 1) / kSlice;
+    const int64_t slots_after = (int64_t)uni.size() * used_slices * kSlice;
+    // (double values of the uniform layout are addressed with 32-bit byte offsets)
+    if ((uni.size() == 4 || uni.size() == 6) && slots_after <= slots_before + slots_before / 4 &&
+        (int64_t)uni.size() * npad * (int64_t)sizeof(double) < (int64_t(1) << 32)) {
+      dia_uniform = (int)uni.size();
+      for (int s = 0; s < nslices; ++s) {
+        nofs[s] = dia_uniform;
+        width[s] = dia_uniform;
+        for (int k = 0; k < dia_uniform; ++k) dia_off[(size_t)s * kDiaMax + k] = uni[k];
+      }
+    }
+  }
   std::vector<int32_t> slice_ptr(nslices + 1, 0);
   int64_t acc = 0;
   int max_width = 0;
@@ -271,6 +309,8 @@ extern "C" gadi_status gadi_setup(const gadi_csr* A, gadi_splitting split, gadi_
   S.nslots = nslots;
   S.max_width = max_width;
   S.dia_slices = dia_slices;
+  S.dia_uniform = dia_uniform;
+  for (int k = 0; k < dia_uniform; ++k) S.dia_u[k] = uni[k];
   int64_t dslots = 0, expl = 0;
   for (int sl = 0; sl < nslices; ++sl) {
     const int64_t slots = (int64_t)(slice_ptr[sl + 1] - slice_ptr[sl]);
@@ -352,6 +392,7 @@ extern "C" gadi_status gadi_get_layout(gadi_handle* h, int64_t* out) {
   out[3] = S.nslots;
   out[4] = S.dia_slots;
   out[5] = S.explicit_entries;
+  out[6] = S.dia_uniform;
   return GADI_OK;
 }
 

@@ -14,14 +14,28 @@
 namespace gadi {
 
 // One large system: persistent cooperative launch, one band of rows per block.
-template <class Mode, int BLOCK, bool FUSED>
+// PW = 0: per-slice layout metadata; PW = 4 or 6: uniformly diagonal-style
+// layout with PW offsets per slice (SolveArgs::dia_u).
+template <class Mode, int BLOCK, bool FUSED, int PW>
 __global__ void __launch_bounds__(BLOCK) solve_kernel(SolveArgs a) {
   GridRed<BLOCK> red{Grid{a.sync, a.flags, a.part, a.result, gridDim.x, 0ull, a.timeout, 0ll}};
   const unsigned lb = logical_block(blockIdx.x, gridDim.x);
   const int t0 = (int)((long long)a.ntiles * lb / gridDim.x);
   const int t1 = (int)((long long)a.ntiles * (lb + 1) / gridDim.x);
   DevInfo r{};
-  if (!solve_body<Mode, BLOCK, FUSED>(a, red, t0, t1, r)) return;
+  bool ok;
+  if constexpr (PW == 0) {
+    // per-slice metadata: a row's loads depend on loaded metadata, one tile at a time
+    const PatGeneric pat{Pattern{a.slice_ptr, a.col, a.slice_dia, a.dia_off, a.n - 1}};
+    ok = solve_body<Mode, BLOCK, FUSED, 1>(a, red, pat, t0, t1, r);
+  } else {
+    PatDia<PW> pat;
+#pragma unroll
+    for (int j = 0; j < PW; ++j) pat.off[j] = a.dia_u[j];
+    pat.nmax = a.n - 1;
+    ok = solve_body<Mode, BLOCK, FUSED, Mode::tiles>(a, red, pat, t0, t1, r);
+  }
+  if (!ok) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     r.barriers = (long long)red.g.epoch;
     r.barrier_ticks = red.g.wait_ticks;
@@ -119,10 +133,10 @@ __global__ void fill_zero_kernel(double* __restrict__ p, long long n) {
 
 gadi_status ensure_fp32_public(System& s) { return ensure_fp32(s); }
 
-template <class Mode, int BLOCK, bool FUSED>
+template <class Mode, int BLOCK, bool FUSED, int PW>
 static gadi_status launch_t(System& s, SolveArgs a, int per_cu) {
   int nb = 0;
-  GADI_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, solve_kernel<Mode, BLOCK, FUSED>, BLOCK, 0));
+  GADI_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, solve_kernel<Mode, BLOCK, FUSED, PW>, BLOCK, 0));
   if (nb < 1 || per_cu > nb) return GADI_EINVAL;  // not co-resident: not a valid shape
   const int ntiles = s.npad / BLOCK;
   long long G = (long long)per_cu * num_cus();
@@ -133,21 +147,29 @@ static gadi_status launch_t(System& s, SolveArgs a, int per_cu) {
   hipLaunchKernelGGL(reset_sync_kernel, dim3(32), dim3(1024), 0, s.stream, s.sync, s.flags, s.info, a.prof);
   GADI_HIP_CHECK(hipGetLastError());
   void* kargs[] = {(void*)&a};
-  GADI_HIP_CHECK(hipLaunchCooperativeKernel((const void*)solve_kernel<Mode, BLOCK, FUSED>, dim3((unsigned)G), dim3(BLOCK),
+  GADI_HIP_CHECK(hipLaunchCooperativeKernel((const void*)solve_kernel<Mode, BLOCK, FUSED, PW>, dim3((unsigned)G), dim3(BLOCK),
                                             kargs, 0, s.stream));
   s.last_blocks = (int)G;
   s.last_block_threads = BLOCK;
   return GADI_OK;
 }
 
-template <class Mode, bool FUSED>
-static gadi_status launch_mode(System& s, const SolveArgs& a, int block, int per_cu) {
+template <class Mode, bool FUSED, int PW>
+static gadi_status launch_block(System& s, const SolveArgs& a, int block, int per_cu) {
   switch (block) {
-    case 256: return launch_t<Mode, 256, FUSED>(s, a, per_cu);
-    case 512: return launch_t<Mode, 512, FUSED>(s, a, per_cu);
-    case 1024: return launch_t<Mode, 1024, FUSED>(s, a, per_cu);
+    case 512: return launch_t<Mode, 512, FUSED, PW>(s, a, per_cu);
+    case 1024: return launch_t<Mode, 1024, FUSED, PW>(s, a, per_cu);
   }
   return GADI_EINVAL;
+}
+
+template <class Mode, bool FUSED>
+static gadi_status launch_mode(System& s, const SolveArgs& a, int block, int per_cu) {
+  switch (s.dia_uniform) {
+    case 4: return launch_block<Mode, FUSED, 4>(s, a, block, per_cu);
+    case 6: return launch_block<Mode, FUSED, 6>(s, a, block, per_cu);
+  }
+  return launch_block<Mode, FUSED, 0>(s, a, block, per_cu);
 }
 
 // fused: Chronopoulos-Gear inner solves (one reduction per CG step) instead of
@@ -180,8 +202,8 @@ static gadi_status tune_solve(System& s, int prec, SolveArgs a, double* dx) {
     return GADI_OK;
   }
   // {threads per block, blocks per CU, fused inner solves}
-  static const int cand[][3] = {{1024, 1, 0}, {1024, 2, 0}, {512, 4, 0}, {512, 2, 0}, {512, 1, 0}, {256, 4, 0},
-                                {256, 2, 0}, {1024, 1, 1}, {1024, 2, 1}, {512, 4, 1}, {512, 2, 1}, {256, 4, 1}};
+  static const int cand[][3] = {{1024, 1, 0}, {1024, 2, 0}, {512, 4, 0}, {512, 2, 0}, {512, 1, 0},
+                                {1024, 1, 1}, {1024, 2, 1}, {512, 4, 1}, {512, 2, 1}};
   a.maxit_out = a.maxit_out < 3 ? a.maxit_out : 3;
   a.hist = nullptr;
   a.hist_cap = 0;
@@ -284,6 +306,7 @@ extern "C" gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x,
   a.col = s.col;
   a.slice_dia = s.slice_dia;
   a.dia_off = s.dia_off;
+  for (int j = 0; j < kDiaMax; ++j) a.dia_u[j] = s.dia_u[j];
   a.a_off = s.a_off;
   a.a_diag = s.a_diag;
   a.b = db;

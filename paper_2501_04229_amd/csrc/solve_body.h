@@ -15,12 +15,13 @@
 // the exact power-of-two scalings keep every half-precision right-hand side
 // in [1/2, 1) in max norm.
 //
-// The CG recurrences fold the direction update into the product phase:
-// q_{k+1} = K p_{k+1} = K r_{k+1} + beta q_k, so each CG step needs two
-// reductions and one operator product.
+// Each phase runs over the rows a block owns and ends in one reduction (a
+// device-wide barrier under the cooperative launch, a block barrier in the
+// batched launch).
 #pragma once
 
 #include <cmath>
+#include <type_traits>
 
 #include "device_common.h"
 
@@ -32,6 +33,9 @@ struct SolveArgs {
   const int32_t* col;
   const int32_t* slice_dia;
   const int32_t* dia_off;
+  // column offsets shared by every slice when the layout is uniformly
+  // diagonal-style (System::dia_uniform slots per slice), else unused
+  int32_t dia_u[kDiaMax];
   const double* a_off;
   const double* a_diag;
   const void* h_off;
@@ -145,25 +149,8 @@ struct BlockRed {
 
 static __device__ __forceinline__ int clamp_exp(int e) { return e < -120 ? -120 : (e > 120 ? 120 : e); }
 
-// The refinement loop of Algorithm 1 for rows [t0 * BLOCK, t1 * BLOCK) of one
-// system.  Returns false if a barrier timed out; otherwise fills `res`.
-//
-// Both inner solves use the Chronopoulos-Gear form of CG: with w = K r and
-// s = K p carried by recurrence, the two inner products of a step,
-// gamma = r.r and delta = r.K r, come from one reduction.  Step k updates
-//   s_k = w_k + beta_k s_{k-1},  p_k = r_k + beta_k p_{k-1},
-//   z += a_k p_k,  r_{k+1} = r_k - a_k s_k,  w_{k+1} = K r_{k+1},
-// with beta_k = gamma_k / gamma_{k-1} and a_k = gamma_k / (delta_k - beta_k gamma_k / a_{k-1}).
-// (FUSED = true.)  The other variant (FUSED = false) is Hestenes-Stiefel CG
-// with q_{k+1} = K p_{k+1} = K r_{k+1} + beta q_k folded into the product
-// phase: two phases per CG step, three per CGNE step, but no recomputation.
-// The product K r_{k+1} needs r_{k+1} at neighbouring rows, which other
-// blocks are writing in the same phase; each block recomputes those values
-// from r_k, w_k, s_{k-1} (read from the previous phase's buffers, hence
-// ping-pong buffers for r, w, s) with the same fused operations and the same
-// roundings as their owner, so every copy is bit-identical.  A CG step on
-// alpha I + H is one phase; a CGNE step on I - (S/alpha)^2 is two (the
-// second product needs the first one's result at neighbouring rows).
+// fused multiply-add in the arithmetic type (fixes the rounding of the
+// recomputed r_{k+1})
 template <class AT>
 __device__ __forceinline__ AT fma_at(AT a, AT b, AT c);
 template <>
@@ -175,26 +162,164 @@ __device__ __forceinline__ double fma_at<double>(double a, double b, double c) {
   return fma(a, b, c);
 }
 
-template <class Mode, int BLOCK, bool FUSED, class Red>
-__device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0, int t1, DevInfo& res_out) {
+// Sparsity-pattern policies of the row products, in two steps so that a
+// phase can issue every load of a row before any arithmetic: gather(row, val,
+// load) returns the row's stored values and load(c) for each of its columns;
+// dot<AT>(g, eval) returns sum_j val_j * eval(load(c_j)) in slot order.
+// PatDia<W> serves a uniformly diagonal-style layout: W slots per slice with
+// the same column offsets in every slice, held in scalar registers, so no
+// address depends on loaded metadata.  PatGeneric reads the per-slice layout
+// metadata (explicit or diagonal-style slices); its gather only records the
+// row and the loads happen inside dot.
+// Element i of p addressed as p plus a 32-bit byte offset, so that a load or
+// store takes a scalar base and one 32-bit offset register (every array the
+// solver indexes this way is below 4 GiB).
+template <class T>
+__device__ __forceinline__ const T& at(const T* p, unsigned i) {
+  return *(const T*)((const char*)p + i * (unsigned)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ T& at(T* p, unsigned i) {
+  return *(T*)((char*)p + i * (unsigned)sizeof(T));
+}
+
+template <int W>
+struct PatDia {
+  int off[W];
+  int nmax;
+  template <class MT, class R>
+  struct G {
+    MT v[W];
+    R x[W];
+  };
+  // Indices are unsigned 32-bit so that loads address from a scalar base
+  // plus a 32-bit offset (every array here is below 4 GiB).
+  template <class MT, class LD>
+  __device__ __forceinline__ auto gather(unsigned row, const MT* __restrict__ val, LD&& load) const {
+    G<MT, decltype(load(0u))> g;
+    // slice s starts at s * W * kSlice; slot j of lane l at + j * kSlice + l
+    const unsigned k0 = (row & ~(unsigned)(kSlice - 1)) * W + (row & (kSlice - 1));
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      g.v[j] = at(val, k0 + j * kSlice);
+      const int cc = (int)row + off[j];
+      g.x[j] = load((unsigned)(cc < 0 ? 0 : (cc > nmax ? nmax : cc)));
+    }
+    return g;
+  }
+  template <class AT, class Gt, class EV>
+  __device__ __forceinline__ AT dot(const Gt& g, EV&& eval) const {
+    AT acc = 0;
+#pragma unroll
+    for (int j = 0; j < W; ++j) acc += ld<AT>(g.v[j]) * eval(g.x[j]);
+    return acc;
+  }
+};
+
+struct PatGeneric {
+  Pattern p;
+  template <class MT, class LD>
+  struct G {
+    int row;
+    const MT* val;
+    LD load;
+  };
+  template <class MT, class LD>
+  __device__ __forceinline__ G<MT, std::decay_t<LD>> gather(unsigned row, const MT* __restrict__ val, LD&& load) const {
+    return {(int)row, val, load};
+  }
+  template <class AT, class Gt, class EV>
+  __device__ __forceinline__ AT dot(const Gt& g, EV&& eval) const {
+    return row_sum<AT>(g.row, p, g.val, [&](unsigned c) { return eval(g.load(c)); });
+  }
+};
+
+// Runs one phase over this thread's rows in three steps per row: load(row)
+// performs every load of the row, math(l) the arithmetic, store(row, out)
+// the writes and the row's terms of the thread's partial sums.  The loads of
+// U tiles are issued before any of their arithmetic (a scheduling barrier
+// keeps the compiler from interleaving them), so a wavefront has all of them
+// in flight at once; partial sums still run over the rows in ascending order.
+template <int BLOCK, int U, class L, class M, class S>
+__device__ __forceinline__ void for_rows(int t0, int t1, L&& load, M&& math, S&& store) {
+  const unsigned tid = threadIdx.x;
+  int t = t0;
+  if constexpr (U > 1) {
+    using LT = decltype(load(0u));
+    for (; t + U <= t1; t += U) {
+      LT l[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) l[u] = load((unsigned)(t + u) * BLOCK + tid);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < U; ++u) store((unsigned)(t + u) * BLOCK + tid, math(l[u]));
+    }
+  }
+  for (; t < t1; ++t) {
+    const unsigned row = (unsigned)t * BLOCK + tid;
+    const auto l = load(row);
+    __builtin_amdgcn_sched_barrier(0);
+    store(row, math(l));
+  }
+}
+
+template <bool B>
+using bool_c = std::integral_constant<bool, B>;
+
+// Calls f(bool_c<true>) when first, else f(bool_c<false>): the first step of
+// a recurrence becomes its own straight-line code instead of a branch per load.
+template <class F>
+__device__ __forceinline__ void first_or_rest(bool first, F&& f) {
+  if (first) f(bool_c<true>{});
+  else f(bool_c<false>{});
+}
+
+template <class T>
+__device__ __forceinline__ T* pick(int k, T* p0, T* p1) {
+  return (k & 1) ? p1 : p0;
+}
+
+// The refinement loop of Algorithm 1 for rows [t0 * BLOCK, t1 * BLOCK) of one
+// system.  Returns false if a barrier timed out; otherwise fills `res`.
+//
+// Both inner solves exist in two forms.  FUSED = true: the Chronopoulos-Gear
+// form of CG: with w = K r and s = K p carried by recurrence, the two inner
+// products of a step, gamma = r.r and delta = r.K r, come from one reduction.
+// Step k updates
+//   s_k = w_k + beta_k s_{k-1},  p_k = r_k + beta_k p_{k-1},
+//   z += a_k p_k,  r_{k+1} = r_k - a_k s_k,  w_{k+1} = K r_{k+1},
+// with beta_k = gamma_k / gamma_{k-1} and a_k = gamma_k / (delta_k - beta_k gamma_k / a_{k-1}).
+// The product K r_{k+1} needs r_{k+1} at neighbouring rows, which other
+// blocks are writing in the same phase; each block recomputes those values
+// from r_k, w_k, s_{k-1} (read from the previous phase's buffers, hence
+// ping-pong buffers for r, w, s) with the same fused operations and the same
+// roundings as their owner, so every copy is bit-identical.  A CG step on
+// alpha I + H is one phase; a CGNE step on I - (S/alpha)^2 is two (the
+// second product needs the first one's result at neighbouring rows).
+// FUSED = false: Hestenes-Stiefel CG with q_{k+1} = K p_{k+1} = K r_{k+1} +
+// beta q_k folded into the product phase: two phases per CG step, three per
+// CGNE step, and no recomputation.
+template <class Mode, int BLOCK, bool FUSED, int U, class Red, class Pat>
+__device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const Pat& pat, int t0, int t1,
+                                           DevInfo& res_out) {
   using MT = typename Mode::MT;
   using VT = typename Mode::VT;
   using ST = typename Mode::ST;
   using RT = typename Mode::RT;
   using AT = typename Mode::AT;
 
-  const int tid = threadIdx.x;
-
-  const Pattern pat{a.slice_ptr, a.col, a.slice_dia, a.dia_off, a.n - 1};
   const MT* __restrict__ hoff = (const MT*)a.h_off;
   const MT* __restrict__ soff = (const MT*)a.s_off;
   const MT* __restrict__ hdiag = (const MT*)a.h_diag;
   RT* __restrict__ r = (RT*)a.r;
   ST* __restrict__ z = (ST*)a.z;
   ST* __restrict__ wsol = (ST*)a.w;
-  VT* const R[2] = {(VT*)a.v[0], (VT*)a.v[1]};
-  VT* const W[2] = {(VT*)a.v[2], (VT*)a.v[3]};
-  VT* const Sv[2] = {(VT*)a.v[4], (VT*)a.v[5]};
+  VT* const R0 = (VT*)a.v[0];
+  VT* const R1 = (VT*)a.v[1];
+  VT* const W0 = (VT*)a.v[2];
+  VT* const W1 = (VT*)a.v[3];
+  VT* const S0 = (VT*)a.v[4];
+  VT* const S1 = (VT*)a.v[5];
   VT* __restrict__ P = (VT*)a.v[6];
   VT* __restrict__ T = (VT*)a.v[7];
   double* __restrict__ x = a.x;
@@ -209,6 +334,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
 
   // value rounded to the storage type and read back
   auto rnd = [](AT v) { return ld<AT>(st<VT>(v)); };
+  auto ldv = [](VT v) { return ld<AT>(v); };
 
   double out[4];
   long long t_mark = (a.prof && blockIdx.x == 0 && threadIdx.x == 0) ? wall_clock64() : 0;
@@ -217,26 +343,44 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
   int sweep = 0;
   long long ih = 0, is = 0;
 
+  // Operands of the recomputed r_{k+1} at a neighbouring row (fused form).
+  struct Rk3 {
+    VT sp, w, r;
+  };
+  struct Rk2 {
+    VT w, r;
+  };
+
   for (;;) {
     // ---------------------------------------------------------- a1: residual
     {
       double s0 = 0.0, m3 = 0.0;
-      for (int t = t0; t < t1; ++t) {
-        const int row = t * BLOCK + tid;
-        const double ax = a.a_diag[row] * x[row] +
-                          row_sum<double>(row, pat, a.a_off, [&](int c) { return x[c]; });
-        const double ri = b[row] - ax;
-        r[row] = (RT)ri;
-        s0 += ri * ri;
-        m3 = fmax(m3, fabs(ri));
-      }
+      auto gx = [&](unsigned c) { return at(x, c); };
+      for_rows<BLOCK, U>(
+          t0, t1,
+          [&](unsigned row) {
+            struct {
+              double d, xr, br;
+              decltype(pat.gather(0u, a.a_off, gx)) g;
+            } l{at(a.a_diag, row), at(x, row), at(b, row), pat.gather(row, a.a_off, gx)};
+            return l;
+          },
+          [&](const auto& l) {
+            const double ax = l.d * l.xr + pat.template dot<double>(l.g, [](double v) { return v; });
+            return l.br - ax;
+          },
+          [&](unsigned row, double ri) {
+            at(r, row) = (RT)ri;
+            s0 += ri * ri;
+            m3 = fmax(m3, fabs(ri));
+          });
       ALLREDUCE_P(0, s0, 0.0, 0.0, m3);
     }
     const double rho = sqrt(out[0]);
     const double rmax = out[3];
     if (sweep == 0) rho0 = rho;
     res = rho0 > 0.0 ? rho / rho0 : 0.0;
-    if (a.hist && sweep < a.hist_cap && blockIdx.x == 0 && tid == 0) a.hist[sweep] = res;
+    if (a.hist && sweep < a.hist_cap && blockIdx.x == 0 && threadIdx.x == 0) a.hist[sweep] = res;
     if (rho <= a.tol * rho0) {
       status = GADI_OK;
       break;
@@ -264,21 +408,35 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
     const AT sc1 = (AT)ldexp(1.0, -e1);
     double zmax = 0.0;
     int it = 0;
+    auto gr = [&](unsigned c) { return at(r, c); };
     if constexpr (FUSED) {
+      struct RW {
+        AT r, w;
+      };
       {
         // r_0 = r * 2^-e1 in storage precision, w_0 = K r_0
         double g0 = 0.0, d0 = 0.0;
-        for (int t = t0; t < t1; ++t) {
-          const int row = t * BLOCK + tid;
-          const AT ri = rnd((AT)r[row] * sc1);
-          const AT kr = (alpha + ld<AT>(hdiag[row])) * ri +
-                        row_sum<AT>(row, pat, hoff, [&](int c) { return rnd((AT)r[c] * sc1); });
-          const AT wi = rnd(kr);
-          R[0][row] = st<VT>(ri);
-          W[0][row] = st<VT>(wi);
-          g0 += (double)ri * (double)ri;
-          d0 += (double)wi * (double)ri;
-        }
+        for_rows<BLOCK, U>(
+            t0, t1,
+            [&](unsigned row) {
+              struct {
+                RT rr;
+                MT hd;
+                decltype(pat.gather(0u, hoff, gr)) g;
+              } l{at(r, row), at(hdiag, row), pat.gather(row, hoff, gr)};
+              return l;
+            },
+            [&](const auto& l) {
+              const AT ri = rnd((AT)l.rr * sc1);
+              const AT kr = (alpha + ld<AT>(l.hd)) * ri + pat.template dot<AT>(l.g, [&](RT v) { return rnd((AT)v * sc1); });
+              return RW{ri, rnd(kr)};
+            },
+            [&](unsigned row, const RW& o) {
+              at(R0, row) = st<VT>(o.r);
+              at(W0, row) = st<VT>(o.w);
+              g0 += (double)o.r * (double)o.r;
+              d0 += (double)o.w * (double)o.r;
+            });
         ALLREDUCE_P(1, g0, d0, 0.0, 0.0);
       }
       double gam = out[0], del = out[1];
@@ -294,35 +452,81 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
           }
           const double ak = gam / den;
           const AT akt = (AT)ak, bkt = (AT)beta;
-          const VT* __restrict__ rk = R[k & 1];
-          const VT* __restrict__ wk = W[k & 1];
-          const VT* __restrict__ sprev = Sv[(k + 1) & 1];
-          VT* __restrict__ snew = Sv[k & 1];
-          VT* __restrict__ rnew = R[(k + 1) & 1];
-          VT* __restrict__ wnew = W[(k + 1) & 1];
-          // r_{k+1} at row c, computed exactly as its owner computes it
-          auto r_next = [&](int c) {
-            const AT sc = k == 0 ? ld<AT>(wk[c]) : rnd(fma_at<AT>(bkt, ld<AT>(sprev[c]), ld<AT>(wk[c])));
-            return rnd(fma_at<AT>(-akt, sc, ld<AT>(rk[c])));
-          };
+          const VT* __restrict__ rk = pick(k, R0, R1);
+          const VT* __restrict__ wk = pick(k, W0, W1);
+          const VT* __restrict__ sprev = pick(k + 1, S0, S1);
+          VT* __restrict__ snew = pick(k, S0, S1);
+          VT* __restrict__ rnew = pick(k + 1, R0, R1);
+          VT* __restrict__ wnew = pick(k + 1, W0, W1);
           double g1 = 0.0, d1 = 0.0, m3 = 0.0;
-          for (int t = t0; t < t1; ++t) {
-            const int row = t * BLOCK + tid;
-            const AT ri = ld<AT>(rk[row]);
-            const AT si = k == 0 ? ld<AT>(wk[row]) : rnd(fma_at<AT>(bkt, ld<AT>(sprev[row]), ld<AT>(wk[row])));
-            const AT pi = k == 0 ? ri : rnd(fma_at<AT>(bkt, ld<AT>(P[row]), ri));
-            const ST zi = (k == 0 ? ST(0) : z[row]) + (ST)(akt * pi);
-            const AT rn = rnd(fma_at<AT>(-akt, si, ri));
-            const AT kr = (alpha + ld<AT>(hdiag[row])) * rn + row_sum<AT>(row, pat, hoff, r_next);
-            const AT wn = rnd(kr);
-            snew[row] = st<VT>(si);
-            P[row] = st<VT>(pi);
-            z[row] = zi;
-            rnew[row] = st<VT>(rn);
-            wnew[row] = st<VT>(wn);
-            g1 += (double)rn * (double)rn;
-            d1 += (double)wn * (double)rn;
-            m3 = fmax(m3, fabs((double)zi));
+          struct O {
+            AT s, p, rn, wn;
+            ST z;
+          };
+          auto store = [&](unsigned row, const O& o) {
+            at(snew, row) = st<VT>(o.s);
+            at(P, row) = st<VT>(o.p);
+            at(z, row) = o.z;
+            at(rnew, row) = st<VT>(o.rn);
+            at(wnew, row) = st<VT>(o.wn);
+            g1 += (double)o.rn * (double)o.rn;
+            d1 += (double)o.wn * (double)o.rn;
+            m3 = fmax(m3, fabs((double)o.z));
+          };
+          if (k == 0) {
+            // s_0 = w_0, p_0 = r_0; r_1 at row c = r_0 - a_0 w_0
+            auto gl = [&](unsigned c) { return Rk2{at(wk, c), at(rk, c)}; };
+            auto r_next = [&](const Rk2& v) { return rnd(fma_at<AT>(-akt, ldv(v.w), ldv(v.r))); };
+            for_rows<BLOCK, U>(
+                t0, t1,
+                [&](unsigned row) {
+                  struct {
+                    VT r, w;
+                    MT hd;
+                    decltype(pat.gather(0u, hoff, gl)) g;
+                  } l{at(rk, row), at(wk, row), at(hdiag, row), pat.gather(row, hoff, gl)};
+                  return l;
+                },
+                [&](const auto& l) {
+                  O o;
+                  const AT ri = ldv(l.r);
+                  o.s = ldv(l.w);
+                  o.p = ri;
+                  o.z = (ST)(akt * ri);
+                  o.rn = rnd(fma_at<AT>(-akt, o.s, ri));
+                  o.wn = rnd((alpha + ld<AT>(l.hd)) * o.rn + pat.template dot<AT>(l.g, r_next));
+                  return o;
+                },
+                store);
+          } else {
+            // s_k = w_k + b_k s_{k-1} and r_{k+1} = r_k - a_k s_k at row c,
+            // computed exactly as the row's owner computes them
+            auto gl = [&](unsigned c) { return Rk3{at(sprev, c), at(wk, c), at(rk, c)}; };
+            auto r_next = [&](const Rk3& v) {
+              return rnd(fma_at<AT>(-akt, rnd(fma_at<AT>(bkt, ldv(v.sp), ldv(v.w))), ldv(v.r)));
+            };
+            for_rows<BLOCK, U>(
+                t0, t1,
+                [&](unsigned row) {
+                  struct {
+                    VT r, w, sp, p;
+                    ST z;
+                    MT hd;
+                    decltype(pat.gather(0u, hoff, gl)) g;
+                  } l{at(rk, row), at(wk, row), at(sprev, row), at(P, row), at(z, row), at(hdiag, row), pat.gather(row, hoff, gl)};
+                  return l;
+                },
+                [&](const auto& l) {
+                  O o;
+                  const AT ri = ldv(l.r);
+                  o.s = rnd(fma_at<AT>(bkt, ldv(l.sp), ldv(l.w)));
+                  o.p = rnd(fma_at<AT>(bkt, ldv(l.p), ri));
+                  o.z = l.z + (ST)(akt * o.p);
+                  o.rn = rnd(fma_at<AT>(-akt, o.s, ri));
+                  o.wn = rnd((alpha + ld<AT>(l.hd)) * o.rn + pat.template dot<AT>(l.g, r_next));
+                  return o;
+                },
+                store);
           }
           ALLREDUCE_P(2, g1, d1, 0.0, m3);
           gam_prev = gam;
@@ -335,25 +539,39 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
         }
       }
     } else {
-      VT* __restrict__ vr = R[0];
+      VT* __restrict__ vr = R0;
       VT* __restrict__ vp = P;
-      VT* __restrict__ vq = W[0];
+      VT* __restrict__ vq = W0;
       double pq, rr, rr0;
       {
+        struct O {
+          VT p, q;
+        };
         double s0 = 0.0, s1 = 0.0;
-        for (int t = t0; t < t1; ++t) {
-          const int row = t * BLOCK + tid;
-          const VT pi = st<VT>((AT)r[row] * sc1);
-          const AT api = ld<AT>(pi);
-          const AT kp = (alpha + ld<AT>(hdiag[row])) * api +
-                        row_sum<AT>(row, pat, hoff, [&](int c) { return ld<AT>(st<VT>((AT)r[c] * sc1)); });
-          const VT qi = st<VT>(kp);
-          vr[row] = pi;
-          vp[row] = pi;
-          vq[row] = qi;
-          s0 += (double)api * (double)ld<AT>(qi);
-          s1 += (double)api * (double)api;
-        }
+        for_rows<BLOCK, U>(
+            t0, t1,
+            [&](unsigned row) {
+              struct {
+                RT rr;
+                MT hd;
+                decltype(pat.gather(0u, hoff, gr)) g;
+              } l{at(r, row), at(hdiag, row), pat.gather(row, hoff, gr)};
+              return l;
+            },
+            [&](const auto& l) {
+              const VT pi = st<VT>((AT)l.rr * sc1);
+              const AT kp = (alpha + ld<AT>(l.hd)) * ld<AT>(pi) +
+                            pat.template dot<AT>(l.g, [&](RT v) { return ld<AT>(st<VT>((AT)v * sc1)); });
+              return O{pi, st<VT>(kp)};
+            },
+            [&](unsigned row, const O& o) {
+              at(vr, row) = o.p;
+              at(vp, row) = o.p;
+              at(vq, row) = o.q;
+              const double api = (double)ld<AT>(o.p);
+              s0 += api * (double)ld<AT>(o.q);
+              s1 += api * api;
+            });
         ALLREDUCE_P(1, s0, s1, 0.0, 0.0);
         pq = out[0];
         rr0 = out[1];
@@ -362,22 +580,42 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
       if (rr0 > 0.0) {
         for (;;) {
           if (!(pq > 0.0) || !isfinite(pq)) {
-            if (it == 0) status = isfinite(pq) ? GADI_ENOTSPD : (Mode::id == GADI_PREC_FP16_IR ? GADI_EOVERFLOW16 : GADI_EDIVERGED);
+            if (it == 0) status = isfinite(pq) ? GADI_ENOTSPD : overflow_status;
             break;
           }
           const AT ak = (AT)(rr / pq);
           double s0 = 0.0, m3 = 0.0;
-          for (int t = t0; t < t1; ++t) {
-            const int row = t * BLOCK + tid;
-            const AT pi = ld<AT>(vp[row]);
-            const ST zi = (it == 0 ? ST(0) : z[row]) + (ST)(ak * pi);
-            z[row] = zi;
-            const VT ri = st<VT>(ld<AT>(vr[row]) - ak * ld<AT>(vq[row]));
-            vr[row] = ri;
-            const double dr = (double)ld<AT>(ri);
-            s0 += dr * dr;
-            m3 = fmax(m3, fabs((double)zi));
-          }
+          first_or_rest(it == 0, [&](auto first_c) {
+            constexpr bool FIRST = decltype(first_c)::value;
+            struct O {
+              ST z;
+              VT r;
+            };
+            for_rows<BLOCK, U>(
+                t0, t1,
+                [&](unsigned row) {
+                  struct {
+                    VT p, r, q;
+                    ST z;
+                  } l{at(vp, row), at(vr, row), at(vq, row), FIRST ? ST(0) : at(z, row)};
+                  return l;
+                },
+                [&](const auto& l) {
+                  const AT pi = ldv(l.p);
+                  O o;
+                  if constexpr (FIRST) o.z = (ST)(ak * pi);
+                  else o.z = l.z + (ST)(ak * pi);
+                  o.r = st<VT>(ldv(l.r) - ak * ldv(l.q));
+                  return o;
+                },
+                [&](unsigned row, const O& o) {
+                  at(z, row) = o.z;
+                  at(vr, row) = o.r;
+                  const double dr = (double)ld<AT>(o.r);
+                  s0 += dr * dr;
+                  m3 = fmax(m3, fabs((double)o.z));
+                });
+          });
           ALLREDUCE_P(3, s0, 0.0, 0.0, m3);
           const double rr_new = out[0];
           zmax = out[3];
@@ -386,16 +624,31 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
           const AT beta = (AT)(rr_new / rr);
           rr = rr_new;
           s0 = 0.0;
-          for (int t = t0; t < t1; ++t) {
-            const int row = t * BLOCK + tid;
-            const AT ri = ld<AT>(vr[row]);
-            const AT kr = (alpha + ld<AT>(hdiag[row])) * ri +
-                          row_sum<AT>(row, pat, hoff, [&](int c) { return ld<AT>(vr[c]); });
-            const VT pn = st<VT>(ri + beta * ld<AT>(vp[row]));
-            const VT qn = st<VT>(kr + beta * ld<AT>(vq[row]));
-            vp[row] = pn;
-            vq[row] = qn;
-            s0 += (double)ld<AT>(pn) * (double)ld<AT>(qn);
+          {
+            struct O {
+              VT p, q;
+            };
+            auto gv = [&](unsigned c) { return at(vr, c); };
+            for_rows<BLOCK, U>(
+                t0, t1,
+                [&](unsigned row) {
+                  struct {
+                    VT r, p, q;
+                    MT hd;
+                    decltype(pat.gather(0u, hoff, gv)) g;
+                  } l{at(vr, row), at(vp, row), at(vq, row), at(hdiag, row), pat.gather(row, hoff, gv)};
+                  return l;
+                },
+                [&](const auto& l) {
+                  const AT ri = ldv(l.r);
+                  const AT kr = (alpha + ld<AT>(l.hd)) * ri + pat.template dot<AT>(l.g, ldv);
+                  return O{st<VT>(ri + beta * ldv(l.p)), st<VT>(kr + beta * ldv(l.q))};
+                },
+                [&](unsigned row, const O& o) {
+                  at(vp, row) = o.p;
+                  at(vq, row) = o.q;
+                  s0 += (double)ld<AT>(o.p) * (double)ld<AT>(o.q);
+                });
           }
           ALLREDUCE_P(2, s0, 0.0, 0.0, 0.0);
           pq = out[0];
@@ -416,32 +669,58 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
       (void)frexp((double)two_m_omega * zmax, &e2);
       e2 = clamp_exp(e2);
       const AT sc2 = (AT)ldexp(1.0, -e2);
-      auto g_at = [&](int c) { return rnd(two_m_omega * (AT)z[c] * sc2); };
+      // g = (2 - omega) z 2^-e2 rounded to the storage type, from a loaded z
+      auto g_of = [&](ST zc) { return rnd(two_m_omega * (AT)zc * sc2); };
+      auto gz = [&](unsigned c) { return at(z, c); };
+      auto gT = [&](unsigned c) { return at(T, c); };
       if constexpr (FUSED) {
         // r_0 = g, t = (S/alpha) g
         {
+          struct O {
+            AT g, t;
+          };
           double g0 = 0.0;
-          for (int t = t0; t < t1; ++t) {
-            const int row = t * BLOCK + tid;
-            const AT gi = g_at(row);
-            const AT tv = inv_alpha * row_sum<AT>(row, pat, soff, g_at);
-            R[0][row] = st<VT>(gi);
-            T[row] = st<VT>(tv);
-            g0 += (double)gi * (double)gi;
-          }
+          for_rows<BLOCK, U>(
+              t0, t1,
+              [&](unsigned row) {
+                struct {
+                  ST z;
+                  decltype(pat.gather(0u, soff, gz)) g;
+                } l{at(z, row), pat.gather(row, soff, gz)};
+                return l;
+              },
+              [&](const auto& l) { return O{g_of(l.z), inv_alpha * pat.template dot<AT>(l.g, g_of)}; },
+              [&](unsigned row, const O& o) {
+                at(R0, row) = st<VT>(o.g);
+                at(T, row) = st<VT>(o.t);
+                g0 += (double)o.g * (double)o.g;
+              });
           ALLREDUCE_P(4, g0, 0.0, 0.0, 0.0);
         }
         const double gs0 = out[0];
         // w_0 = r_0 - (S/alpha) t
         {
+          struct O {
+            AT r, w;
+          };
           double d0 = 0.0;
-          for (int t = t0; t < t1; ++t) {
-            const int row = t * BLOCK + tid;
-            const AT ri = ld<AT>(R[0][row]);
-            const AT wi = rnd(ri - inv_alpha * row_sum<AT>(row, pat, soff, [&](int c) { return ld<AT>(T[c]); }));
-            W[0][row] = st<VT>(wi);
-            d0 += (double)wi * (double)ri;
-          }
+          for_rows<BLOCK, U>(
+              t0, t1,
+              [&](unsigned row) {
+                struct {
+                  VT r;
+                  decltype(pat.gather(0u, soff, gT)) g;
+                } l{at(R0, row), pat.gather(row, soff, gT)};
+                return l;
+              },
+              [&](const auto& l) {
+                const AT ri = ldv(l.r);
+                return O{ri, rnd(ri - inv_alpha * pat.template dot<AT>(l.g, ldv))};
+              },
+              [&](unsigned row, const O& o) {
+                at(W0, row) = st<VT>(o.w);
+                d0 += (double)o.w * (double)o.r;
+              });
           ALLREDUCE_P(4, 0.0, d0, 0.0, 0.0);
         }
         double gam = gs0, del = out[1];
@@ -456,31 +735,75 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
             }
             const double ak = gam / den;
             const AT akt = (AT)ak, bkt = (AT)beta;
-            const VT* __restrict__ rk = R[k & 1];
-            const VT* __restrict__ wk = W[k & 1];
-            const VT* __restrict__ sprev = Sv[(k + 1) & 1];
-            VT* __restrict__ snew = Sv[k & 1];
-            VT* __restrict__ rnew = R[(k + 1) & 1];
-            VT* __restrict__ wnew = W[(k + 1) & 1];
-            auto r_next = [&](int c) {
-              const AT sc = k == 0 ? ld<AT>(wk[c]) : rnd(fma_at<AT>(bkt, ld<AT>(sprev[c]), ld<AT>(wk[c])));
-              return rnd(fma_at<AT>(-akt, sc, ld<AT>(rk[c])));
-            };
+            const VT* __restrict__ rk = pick(k, R0, R1);
+            const VT* __restrict__ wk = pick(k, W0, W1);
+            const VT* __restrict__ sprev = pick(k + 1, S0, S1);
+            VT* __restrict__ snew = pick(k, S0, S1);
+            VT* __restrict__ rnew = pick(k + 1, R0, R1);
+            VT* __restrict__ wnew = pick(k + 1, W0, W1);
             // step + t = (S/alpha) r_{k+1}
             double g1 = 0.0;
-            for (int t = t0; t < t1; ++t) {
-              const int row = t * BLOCK + tid;
-              const AT ri = ld<AT>(rk[row]);
-              const AT si = k == 0 ? ld<AT>(wk[row]) : rnd(fma_at<AT>(bkt, ld<AT>(sprev[row]), ld<AT>(wk[row])));
-              const AT pi = k == 0 ? ri : rnd(fma_at<AT>(bkt, ld<AT>(P[row]), ri));
-              wsol[row] = (k == 0 ? ST(0) : wsol[row]) + (ST)(akt * pi);
-              const AT rn = rnd(fma_at<AT>(-akt, si, ri));
-              const AT tv = inv_alpha * row_sum<AT>(row, pat, soff, r_next);
-              snew[row] = st<VT>(si);
-              P[row] = st<VT>(pi);
-              rnew[row] = st<VT>(rn);
-              T[row] = st<VT>(tv);
-              g1 += (double)rn * (double)rn;
+            struct O {
+              AT s, p, rn, t;
+              ST w;
+            };
+            auto store = [&](unsigned row, const O& o) {
+              at(snew, row) = st<VT>(o.s);
+              at(P, row) = st<VT>(o.p);
+              at(wsol, row) = o.w;
+              at(rnew, row) = st<VT>(o.rn);
+              at(T, row) = st<VT>(o.t);
+              g1 += (double)o.rn * (double)o.rn;
+            };
+            if (k == 0) {
+              auto gl = [&](unsigned c) { return Rk2{at(wk, c), at(rk, c)}; };
+              auto r_next = [&](const Rk2& v) { return rnd(fma_at<AT>(-akt, ldv(v.w), ldv(v.r))); };
+              for_rows<BLOCK, U>(
+                  t0, t1,
+                  [&](unsigned row) {
+                    struct {
+                      VT r, w;
+                      decltype(pat.gather(0u, soff, gl)) g;
+                    } l{at(rk, row), at(wk, row), pat.gather(row, soff, gl)};
+                    return l;
+                  },
+                  [&](const auto& l) {
+                    O o;
+                    const AT ri = ldv(l.r);
+                    o.s = ldv(l.w);
+                    o.p = ri;
+                    o.w = (ST)(akt * ri);
+                    o.rn = rnd(fma_at<AT>(-akt, o.s, ri));
+                    o.t = inv_alpha * pat.template dot<AT>(l.g, r_next);
+                    return o;
+                  },
+                  store);
+            } else {
+              auto gl = [&](unsigned c) { return Rk3{at(sprev, c), at(wk, c), at(rk, c)}; };
+              auto r_next = [&](const Rk3& v) {
+                return rnd(fma_at<AT>(-akt, rnd(fma_at<AT>(bkt, ldv(v.sp), ldv(v.w))), ldv(v.r)));
+              };
+              for_rows<BLOCK, U>(
+                  t0, t1,
+                  [&](unsigned row) {
+                    struct {
+                      VT r, w, sp, p;
+                      ST ws;
+                      decltype(pat.gather(0u, soff, gl)) g;
+                    } l{at(rk, row), at(wk, row), at(sprev, row), at(P, row), at(wsol, row), pat.gather(row, soff, gl)};
+                    return l;
+                  },
+                  [&](const auto& l) {
+                    O o;
+                    const AT ri = ldv(l.r);
+                    o.s = rnd(fma_at<AT>(bkt, ldv(l.sp), ldv(l.w)));
+                    o.p = rnd(fma_at<AT>(bkt, ldv(l.p), ri));
+                    o.w = l.ws + (ST)(akt * o.p);
+                    o.rn = rnd(fma_at<AT>(-akt, o.s, ri));
+                    o.t = inv_alpha * pat.template dot<AT>(l.g, r_next);
+                    return o;
+                  },
+                  store);
             }
             ALLREDUCE_P(5, g1, 0.0, 0.0, 0.0);
             gam_prev = gam;
@@ -490,83 +813,165 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
             if (gam <= eps_s2 * gs0 || its >= a.maxit_in || !isfinite(gam)) break;
             // w_{k+1} = r_{k+1} - (S/alpha) t
             double d1 = 0.0;
-            for (int t = t0; t < t1; ++t) {
-              const int row = t * BLOCK + tid;
-              const AT rn = ld<AT>(rnew[row]);
-              const AT wn = rnd(rn - inv_alpha * row_sum<AT>(row, pat, soff, [&](int c) { return ld<AT>(T[c]); }));
-              wnew[row] = st<VT>(wn);
-              d1 += (double)wn * (double)rn;
+            {
+              struct O2 {
+                AT r, w;
+              };
+              for_rows<BLOCK, U>(
+                  t0, t1,
+                  [&](unsigned row) {
+                    struct {
+                      VT r;
+                      decltype(pat.gather(0u, soff, gT)) g;
+                    } l{at(rnew, row), pat.gather(row, soff, gT)};
+                    return l;
+                  },
+                  [&](const auto& l) {
+                    const AT rn = ldv(l.r);
+                    return O2{rn, rnd(rn - inv_alpha * pat.template dot<AT>(l.g, ldv))};
+                  },
+                  [&](unsigned row, const O2& o) {
+                    at(wnew, row) = st<VT>(o.w);
+                    d1 += (double)o.w * (double)o.r;
+                  });
             }
             ALLREDUCE_P(6, 0.0, d1, 0.0, 0.0);
             del = out[1];
           }
         }
       } else {
-        VT* __restrict__ vr = R[0];
+        VT* __restrict__ vr = R0;
         VT* __restrict__ vp = P;
-        VT* __restrict__ vq = W[0];
+        VT* __restrict__ vq = W0;
         VT* __restrict__ vt = T;
         ST* __restrict__ w = wsol;
         double rrs0;
         {
+          struct O {
+            VT g, t;
+          };
           double s1 = 0.0;
-          for (int t = t0; t < t1; ++t) {
-            const int row = t * BLOCK + tid;
-            const VT gi = st<VT>(two_m_omega * (AT)z[row] * sc2);
-            const AT tv = inv_alpha * row_sum<AT>(row, pat, soff, [&](int c) {
-                            return ld<AT>(st<VT>(two_m_omega * (AT)z[c] * sc2));
-                          });
-            vr[row] = gi;
-            vp[row] = gi;
-            vt[row] = st<VT>(tv);
-            const double dg = (double)ld<AT>(gi);
-            s1 += dg * dg;
-          }
+          for_rows<BLOCK, U>(
+              t0, t1,
+              [&](unsigned row) {
+                struct {
+                  ST z;
+                  decltype(pat.gather(0u, soff, gz)) g;
+                } l{at(z, row), pat.gather(row, soff, gz)};
+                return l;
+              },
+              [&](const auto& l) {
+                const VT gi = st<VT>(two_m_omega * (AT)l.z * sc2);
+                const AT tv = inv_alpha * pat.template dot<AT>(l.g, [&](ST zc) {
+                                return ld<AT>(st<VT>(two_m_omega * (AT)zc * sc2));
+                              });
+                return O{gi, st<VT>(tv)};
+              },
+              [&](unsigned row, const O& o) {
+                at(vr, row) = o.g;
+                at(vp, row) = o.g;
+                at(vt, row) = o.t;
+                const double dg = (double)ld<AT>(o.g);
+                s1 += dg * dg;
+              });
           ALLREDUCE_P(4, 0.0, s1, 0.0, 0.0);
           rrs0 = out[1];
         }
         double rrs = rrs0;
         if (rrs0 > 0.0) {
+          auto gvt = [&](unsigned c) { return at(vt, c); };
+          auto gvr = [&](unsigned c) { return at(vr, c); };
           for (;;) {
             // q = p - (S/alpha) t, with t = (S/alpha) p
             double s0 = 0.0;
-            for (int t = t0; t < t1; ++t) {
-              const int row = t * BLOCK + tid;
-              const AT pi = ld<AT>(vp[row]);
-              const AT qv = pi - inv_alpha * row_sum<AT>(row, pat, soff, [&](int c) { return ld<AT>(vt[c]); });
-              const VT qi = st<VT>(qv);
-              vq[row] = qi;
-              s0 += (double)pi * (double)ld<AT>(qi);
+            {
+              struct O {
+                AT p;
+                VT q;
+              };
+              for_rows<BLOCK, U>(
+                  t0, t1,
+                  [&](unsigned row) {
+                    struct {
+                      VT p;
+                      decltype(pat.gather(0u, soff, gvt)) g;
+                    } l{at(vp, row), pat.gather(row, soff, gvt)};
+                    return l;
+                  },
+                  [&](const auto& l) {
+                    const AT pi = ldv(l.p);
+                    return O{pi, st<VT>(pi - inv_alpha * pat.template dot<AT>(l.g, ldv))};
+                  },
+                  [&](unsigned row, const O& o) {
+                    at(vq, row) = o.q;
+                    s0 += (double)o.p * (double)ld<AT>(o.q);
+                  });
             }
             ALLREDUCE_P(6, s0, 0.0, 0.0, 0.0);
             const double pqs = out[0];
             if (!(pqs > 0.0) || !isfinite(pqs)) {
-              if (its == 0) status = isfinite(pqs) ? GADI_ENOTSPD : (Mode::id == GADI_PREC_FP16_IR ? GADI_EOVERFLOW16 : GADI_EDIVERGED);
+              if (its == 0) status = isfinite(pqs) ? GADI_ENOTSPD : overflow_status;
               break;
             }
             const AT ak = (AT)(rrs / pqs);
             s0 = 0.0;
-            for (int t = t0; t < t1; ++t) {
-              const int row = t * BLOCK + tid;
-              const AT pi = ld<AT>(vp[row]);
-              w[row] = (its == 0 ? ST(0) : w[row]) + (ST)(ak * pi);
-              const VT ri = st<VT>(ld<AT>(vr[row]) - ak * ld<AT>(vq[row]));
-              vr[row] = ri;
-              const double dr = (double)ld<AT>(ri);
-              s0 += dr * dr;
-            }
+            first_or_rest(its == 0, [&](auto first_c) {
+              constexpr bool FIRST = decltype(first_c)::value;
+              struct O {
+                ST w;
+                VT r;
+              };
+              for_rows<BLOCK, U>(
+                  t0, t1,
+                  [&](unsigned row) {
+                    struct {
+                      VT p, r, q;
+                      ST w;
+                    } l{at(vp, row), at(vr, row), at(vq, row), FIRST ? ST(0) : at(w, row)};
+                    return l;
+                  },
+                  [&](const auto& l) {
+                    const AT pi = ldv(l.p);
+                    O o;
+                    if constexpr (FIRST) o.w = (ST)(ak * pi);
+                    else o.w = l.w + (ST)(ak * pi);
+                    o.r = st<VT>(ldv(l.r) - ak * ldv(l.q));
+                    return o;
+                  },
+                  [&](unsigned row, const O& o) {
+                    at(w, row) = o.w;
+                    at(vr, row) = o.r;
+                    const double dr = (double)ld<AT>(o.r);
+                    s0 += dr * dr;
+                  });
+            });
             ALLREDUCE_P(7, s0, 0.0, 0.0, 0.0);
             const double rr_new = out[0];
             ++its;
             if (rr_new <= eps_s2 * rrs0 || its >= a.maxit_in || !isfinite(rr_new)) break;
             const AT beta = (AT)(rr_new / rrs);
             rrs = rr_new;
-            for (int t = t0; t < t1; ++t) {
-              const int row = t * BLOCK + tid;
-              const AT ri = ld<AT>(vr[row]);
-              const AT sr = inv_alpha * row_sum<AT>(row, pat, soff, [&](int c) { return ld<AT>(vr[c]); });
-              vt[row] = st<VT>(sr + beta * ld<AT>(vt[row]));
-              vp[row] = st<VT>(ri + beta * ld<AT>(vp[row]));
+            {
+              struct O {
+                VT t, p;
+              };
+              for_rows<BLOCK, U>(
+                  t0, t1,
+                  [&](unsigned row) {
+                    struct {
+                      VT r, t, p;
+                      decltype(pat.gather(0u, soff, gvr)) g;
+                    } l{at(vr, row), at(vt, row), at(vp, row), pat.gather(row, soff, gvr)};
+                    return l;
+                  },
+                  [&](const auto& l) {
+                    const AT sr = inv_alpha * pat.template dot<AT>(l.g, ldv);
+                    return O{st<VT>(sr + beta * ldv(l.t)), st<VT>(ldv(l.r) + beta * ldv(l.p))};
+                  },
+                  [&](unsigned row, const O& o) {
+                    at(vt, row) = o.t;
+                    at(vp, row) = o.p;
+                  });
             }
             ALLREDUCE_P(5, 0.0, 0.0, 0.0, 0.0);
           }
@@ -578,11 +983,22 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, int t0,
       // ---------------------------------------------------------- a6: x += (I - S/alpha) w * 2^(e1+e2)
       if (its > 0) {
         const double unscale = ldexp(1.0, e1 + e2);
-        for (int t = t0; t < t1; ++t) {
-          const int row = t * BLOCK + tid;
-          const AT ui = (AT)wsol[row] - inv_alpha * row_sum<AT>(row, pat, soff, [&](int c) { return (AT)wsol[c]; });
-          x[row] += (double)ui * unscale;
-        }
+        auto gw = [&](unsigned c) { return at(wsol, c); };
+        for_rows<BLOCK, U>(
+            t0, t1,
+            [&](unsigned row) {
+              struct {
+                ST w;
+                double x;
+                decltype(pat.gather(0u, soff, gw)) g;
+              } l{at(wsol, row), at(x, row), pat.gather(row, soff, gw)};
+              return l;
+            },
+            [&](const auto& l) {
+              const AT ui = (AT)l.w - inv_alpha * pat.template dot<AT>(l.g, [](ST v) { return (AT)v; });
+              return l.x + (double)ui * unscale;
+            },
+            [&](unsigned row, double xn) { at(x, row) = xn; });
         ALLREDUCE_P(8, 0.0, 0.0, 0.0, 0.0);
       }
     }

@@ -25,6 +25,21 @@ U16 = 2.0 ** -11
 U32 = 2.0 ** -24
 U64 = 2.0 ** -53
 
+def banded(n, offsets, seed):
+    """Positive-real band matrix: diagonal 2 + 2 len(offsets), symmetric part -1 and
+    a seeded skew part in (-0.5, 0.5) on each offset pair +-d."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    A = sp.diags([np.full(n, 2.0 + 2 * len(offsets))], [0], shape=(n, n), format="lil")
+    for d in offsets:
+        k = rng.uniform(-0.5, 0.5, n - d)
+        A.setdiag(-1.0 + k, d)
+        A.setdiag(-1.0 - k, -d)
+    A = A.tocsr()
+    A.sort_indices()
+    return gi.Csr(n, A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64))
+
+
 CASES = [
     ("2d64_b10", lambda: gi.convdiff(64, 2, 10.0)),
     ("3d17_b", lambda: gi.convdiff(17, 3, (3.0, 40.0, 0.5))),  # 4913 rows: ragged last tile
@@ -33,7 +48,14 @@ CASES = [
     # irregular patterns: every slice stored with explicit columns / a mix of both layouts
     ("2d40_rand", lambda: gi.convdiff_skew_perturbed(40, 2, 5.0, 3.0, 0.2, seed=3)),
     ("3d12_mixed", lambda: gi.convdiff_skew_perturbed(12, 3, 8.0, 2.0, 0.2, seed=4, rows_fraction=0.02)),
+    # every slice diagonal-style, 8 offsets: per-slice metadata without explicit columns
+    ("band8", lambda: banded(3001, (1, 2, 37, 300), seed=5)),
 ]
+
+# expected storage: offsets per slice of the uniform layout (0 = per-slice metadata)
+# and whether explicit columns are stored
+LAYOUT = {"2d64_b10": (4, False), "3d17_b": (6, False), "2d7_b2": (4, False), "3d40_b20": (6, False),
+          "2d40_rand": (0, True), "3d12_mixed": (0, True), "band8": (0, False)}
 
 
 @pytest.fixture(scope="module", params=CASES, ids=[c[0] for c in CASES])
@@ -79,6 +101,30 @@ def test_split_fp16_matches_rounded_oracle(case):
                 assert np.float16(oval[k]).view(np.uint16) == np.float16(dev.get(key, 0.0)).view(np.uint16)
         assert set(k for k, v in dev.items() if v != 0) <= set((i, int(ocol[k])) for i in range(A.n)
                                                                for k in range(orp[i], orp[i + 1]))
+
+
+def test_layout_kind(case, request):
+    """Stencil matrices get the uniform diagonal layout, the others per-slice metadata."""
+    A, g, o = case
+    name = request.node.callspec.id
+    lay = g.layout()
+    w, expl = LAYOUT[name]
+    assert lay["uniform_offsets"] == w
+    assert (lay["explicit_entries"] > 0) == expl
+    assert lay["nnz_off"] == sum(int(c != i) for i in range(A.n) for c in
+                                 set(A.col[A.row_ptr[i]:A.row_ptr[i + 1]]) | set(_transpose_cols(A, i)))
+    if w:
+        assert lay["slots"] == w * lay["npad"] == lay["dia_slots"]
+
+
+def _transpose_cols(A, i):
+    if not hasattr(A, "_tcols"):
+        cols = [[] for _ in range(A.n)]
+        for r in range(A.n):
+            for c in A.col[A.row_ptr[r]:A.row_ptr[r + 1]]:
+                cols[c].append(r)
+        A._tcols = cols
+    return A._tcols[i]
 
 
 def test_spmv_a64(case):
@@ -132,6 +178,8 @@ def test_spmv_s16(case, alpha):
 
 def test_features_match_oracle(case):
     A, g, o = case
+    if not A.grid:
+        pytest.skip("features describe convection-diffusion grids")
     f = g.features(A.dim, A.grid, A.beta)
     fo = oracle.features(A, o.gershgorin())
     assert np.allclose(f, fo, rtol=2e-7, atol=1e-7)
@@ -150,7 +198,12 @@ def parity_tol(A, b, xref, target=1e-8, ref_tol=1e-13):
     because A is positive real; lambda_min(H) is the closed form of the splitting.
     Returns min(1e-10, the largest tol meeting the target)."""
     from oracle import dense as od
-    lmin = od.convdiff_eigs_H(A.grid, A.dim)[0]
+    if A.grid:
+        lmin = od.convdiff_eigs_H(A.grid, A.dim)[0]
+    else:
+        # Gershgorin: lambda_min(H) >= min_i (H_ii - sum_j |H_ij|), positive for these matrices
+        lmin = oracle.OracleSystem(A).gershgorin()[0]
+        assert lmin > 0
     t = target * lmin * np.linalg.norm(xref) / np.linalg.norm(b) - ref_tol
     return min(1e-10, 0.9 * t)
 
