@@ -166,7 +166,7 @@ def main():
         psrc = "mlp"
 
     def run(prec, al, om, e):
-        """One step: with the predictor, solve_auto (prediction judged by the default);
+        """One step: with the predictor, solve_auto (prediction guarded by the default);
         without, a plain solve.  Returns (x, info, launches, used)."""
         if pred is not None and prec == args.prec:
             x, info, used = pr.solve_auto(g, A, bd, pred, tol=1e-10, prec=prec, eps_inner=e)

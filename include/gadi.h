@@ -154,11 +154,13 @@ gadi_status gadi_spmv(gadi_handle* h, int32_t which, double alpha, const void* x
 gadi_status gadi_get_split_fp16(gadi_handle* h, int32_t which, int32_t* out_rp, int32_t* out_col,
                                 uint16_t* out_val, int64_t* nnz_out);
 
-/* Predictor features (computed on the device from the packed splitting):
- * out[8] = [ln n, dim, log10 mean(beta), log10(max(beta) h/2) with h = 1/(grid+1)
- *           (the cell Peclet number), min_i(H_ii - R_i^H), max_i(H_ii + R_i^H),
- *           log10 max_i R_i^S, log10 min_i R_i^S],
- * R_i the off-diagonal absolute row sums; log10 arguments floored at 1e-12.  dim, grid and beta[dim] describe the
+/* Predictor features (the row sums computed on the device from the packed
+ * splitting): out[8] = [ln n, dim, log10 mean(beta), log10(max(beta) h/2) with
+ * h = 1/(grid+1) (the cell Peclet number), log10 lambda_min(H) with
+ * lambda_min(H) = dim (2 - 2 cos(pi h)) (closed form for the h^2-scaled
+ * Laplacian), log10 max_i(H_ii + R_i^H) (Gershgorin bound of lambda_max(H)),
+ * log10 max_i R_i^S, log10 min_i R_i^S], R_i the off-diagonal absolute row
+ * sums; log10 arguments floored at 1e-12.  dim, grid and beta[dim] describe the
  * convection-diffusion problem (Section 4.1) and are caller-supplied. */
 gadi_status gadi_features(gadi_handle* h, int32_t dim, int32_t grid, const double* beta, float* out);
 
@@ -192,8 +194,12 @@ gadi_status gadi_mlp_loss_grad(gadi_mlp* m, const float* Xs, const float* Y, int
  * before each step.  All arithmetic runs in the device kernels. */
 gadi_status gadi_train_mlp(gadi_mlp* m, const float* X, const float* Y, int32_t n, int32_t epochs,
                            float lr, float* loss_out);
-/* Predict (alpha, omega) for one raw feature vector; alpha is clamped to
- * [1e-3, 10] and omega to [0, 1.99]. */
+/* Predict (alpha, omega) for one raw feature vector (gadi_features' layout).
+ * The network's outputs are y0 = log10(alpha / alpha_ref) and y1 = omega, with
+ * alpha_ref = sqrt(lambda_min(H) lambda_max(H)) = 10^((f[4] + f[5]) / 2) taken
+ * from the unclamped features, so that the spectral scale follows the system
+ * size even where the network's inputs are clamped to the training range.
+ * alpha is clamped to [1e-3, 10] and omega to [0, 1.99]. */
 gadi_status gadi_predict_params(gadi_mlp* m, const float* features, double* alpha, double* omega);
 
 /* Release the handle and its device memory. */

@@ -169,9 +169,11 @@ def features(A, gersh=None) -> np.ndarray:
     """Predictor features of a convection-diffusion system.
 
     [ln N, dim, log10 mean(beta), log10 Pe with Pe = max_a beta_a h / 2,
-     min_i(H_ii - R_i^H), max_i(H_ii + R_i^H), log10 max_i R_i^S, log10 min_i R_i^S]
-    with h = 1/(n+1), R_i the off-diagonal absolute row sums of H, S, and the
-    log10 arguments floored at 1e-12.
+     log10 lambda_min(H), log10 max_i(H_ii + R_i^H), log10 max_i R_i^S, log10 min_i R_i^S]
+    with h = 1/(n+1), lambda_min(H) = dim (2 - 2 cos(pi h)) (the smallest
+    eigenvalue of the h^2-scaled Laplacian, Section 4.1's symmetric part), R_i
+    the off-diagonal absolute row sums of H, S, and the log10 arguments
+    floored at 1e-12.
     """
     if gersh is None:
         gersh = OracleSystem(A).gershgorin()
@@ -181,4 +183,5 @@ def features(A, gersh=None) -> np.ndarray:
     def lg(v):
         return math.log10(max(v, 1e-12))
     return np.array([math.log(A.n), float(A.dim), math.log10(float(beta.mean())),
-                     lg(float(beta.max()) * h / 2.0), gersh[0], gersh[1], lg(gersh[2]), lg(gersh[3])])
+                     lg(float(beta.max()) * h / 2.0), lg(A.dim * (2.0 - 2.0 * math.cos(math.pi * h))),
+                     lg(gersh[1]), lg(gersh[2]), lg(gersh[3])])

@@ -448,7 +448,11 @@ extern "C" gadi_status gadi_predict_params(gadi_mlp* m, const float* features, d
   gadi_status st = gadi_mlp_forward(m, features, 1, y);
   if (st != GADI_OK) return st;
   if (!std::isfinite(y[0]) || !std::isfinite(y[1])) return GADI_EINVAL;
-  double a = std::pow(10.0, (double)y[0]);
+  // the first output is log10(alpha / alpha_ref) with alpha_ref = sqrt(lambda_min
+  // lambda_max) from the unclamped features 4 and 5 (log10 of H's spectral
+  // bounds), so the spectral scale follows the system size beyond the
+  // training range
+  double a = std::pow(10.0, (double)y[0] + 0.5 * ((double)features[4] + (double)features[5]));
   a = a < 1e-3 ? 1e-3 : (a > 10.0 ? 10.0 : a);
   double w = y[1] < 0.f ? 0.0 : (y[1] > 1.99f ? 1.99 : (double)y[1]);
   *alpha = a;

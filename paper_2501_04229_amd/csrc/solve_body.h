@@ -55,8 +55,9 @@ struct SolveArgs {
   DevInfo* info;
   double* hist;
   long long timeout;
-  // Batched sweeps only: best work (operator products) of a converged trial
-  // of this system so far; a trial stops (EMAXIT) once its own work exceeds it.
+  // Batched sweeps only: least work of a converged trial of this system so
+  // far, in phases of the fused inner solvers (a CG step 1, a CGNE step 2,
+  // the rest of a sweep 5); a trial stops (EMAXIT) once its own work exceeds it.
   unsigned long long* prune;
   // optional per-phase profile of block 0: wall-clock ticks [10], phase counts [10]
   long long* prof;
@@ -394,7 +395,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
       break;
     }
     if (a.prune) {
-      const unsigned long long wk = (unsigned long long)(ih + 2 * is + 3 * (long long)sweep);
+      const unsigned long long wk = (unsigned long long)(ih + 2 * is + 5 * (long long)sweep);
       if (wk > red.broadcast_load(a.prune)) {
         status = GADI_EMAXIT;
         break;
@@ -1006,7 +1007,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
   }
 
   if (a.prune && status == GADI_OK)
-    red.publish_min(a.prune, (unsigned long long)(ih + 2 * is + 3 * (long long)sweep));
+    red.publish_min(a.prune, (unsigned long long)(ih + 2 * is + 5 * (long long)sweep));
   res_out.status = status;
   res_out.sweeps = sweep;
   res_out.inner_h = ih;

@@ -152,8 +152,12 @@ extern "C" gadi_status gadi_features(gadi_handle* h, int32_t dim, int32_t grid, 
   // scale-free quantities enter in log10 (floored at 1e-12 so beta = 0 stays finite)
   auto lg = [](double v) { return std::log10(v > 1e-12 ? v : 1e-12); };
   out[3] = (float)lg(bmax * hgrid / 2.0);
-  out[4] = (float)g0;
-  out[5] = (float)g1;
+  // spectral scale of H: its smallest eigenvalue in closed form (a sum of
+  // 1-D h^2-scaled Laplacians: dim (2 - 2 cos(pi h))) and the Gershgorin
+  // bound of its largest
+  (void)g0;
+  out[4] = (float)lg(dim * (2.0 - 2.0 * std::cos(M_PI * hgrid)));
+  out[5] = (float)lg(g1);
   out[6] = (float)lg(g2);
   out[7] = (float)lg(g3);
   return GADI_OK;

@@ -8,17 +8,23 @@ set comes from the batched (alpha, omega) sweep of libgadi on small
 convection-diffusion systems.
 
 Label of a system: the trial with the least solver work among the trials that
-reached the tolerance, where work = inner_H + 2 inner_S + 3 sweeps counts
-operator products (a CG step applies alpha I + H once, a CGNE step applies S
-twice, each sweep adds the residual, the first CG product and the update).
-Ties go to fewer outer sweeps, then to the larger alpha.  Targets are
-(log10 alpha, omega).
+reached the tolerance, where work = inner_H + 2 inner_S + 5 sweeps counts the
+phases of the persistent solve kernel with the fused inner solvers (a CG step
+is one phase, a CGNE step two, and each sweep adds the residual, the CG start,
+the two CGNE start phases and the update).  Each phase ends in a device-wide
+reduction, and on the large systems the solve time is proportional to this
+count.  Ties go to fewer outer sweeps, then to the larger alpha.
 
-The default parameters (0.5, 0.5) are both the fallback and the judge:
-`solve_auto` probes both for a few sweeps, projects each one's remaining time
-from its measured contraction rate, and continues the faster one from its own
-iterate, so a prediction that would need more time than the default is
-rejected at the cost of its probe.
+Targets are (log10(alpha / alpha_ref), omega) with alpha_ref =
+sqrt(lambda_min(H) lambda_max(H)) from features 4 and 5 (the optimal HSS
+parameter of the symmetric part alone), so the network learns a scale-free
+correction and the size dependence of alpha comes from the closed-form
+spectrum; libgadi applies alpha = alpha_ref 10^y0 at prediction time.
+
+The default parameters (0.5, 0.5) are the fallback: `solve_auto` runs the
+prediction for a few sweeps and replaces it by the default only if that run
+fails or its measured contraction rate cannot reach the tolerance within the
+sweep budget.
 """
 from __future__ import annotations
 
@@ -43,8 +49,13 @@ def trial_grid():
 
 
 def work(rec) -> float:
-    """Operator products of a solve record."""
-    return float(rec["inner_H"] + 2 * rec["inner_S"] + 3 * rec["outer_sweeps"])
+    """Phases of the fused solve kernel for a solve record."""
+    return float(rec["inner_H"] + 2 * rec["inner_S"] + 5 * rec["outer_sweeps"])
+
+
+def log_alpha_ref(f) -> float:
+    """log10 sqrt(lambda_min(H) lambda_max(H)) from a feature vector."""
+    return 0.5 * (float(f[4]) + float(f[5]))
 
 
 def label(recs):
@@ -105,7 +116,7 @@ def dataset(recs, feats):
         if t is None:
             continue
         X.append(f)
-        Y.append([math.log10(r[t]["alpha"]), r[t]["omega"]])
+        Y.append([math.log10(r[t]["alpha"]) - log_alpha_ref(f), r[t]["omega"]])
     return np.asarray(X, np.float32), np.asarray(Y, np.float32)
 
 
@@ -180,44 +191,45 @@ def _projected_sweeps(hist, tol):
     return max(0.0, (math.log(tol) - math.log(h[-1])) / slope)
 
 
-def solve_auto(system, A, b, predictor, tol=1e-10, probe=48, margin=0.9, **kw):
-    """Solve with the predicted (alpha, omega), judged by the default (0.5, 0.5).
+def solve_auto(system, A, b, predictor, tol=1e-10, probe=32, **kw):
+    """Solve with the predicted (alpha, omega), guarded by the default (0.5, 0.5).
 
-    Both candidates run `probe` sweeps; each projects its remaining time from
-    its measured contraction rate and time per sweep; the prediction is kept
-    only if its projection is below `margin` times the default's, and the kept
-    candidate continues from its own iterate (warm start), so a rejected
-    prediction costs only its probe.  Returns (x, info, used) with used in
-    {'mlp', 'default'}; info sums sweeps, inner steps and device seconds over
-    every launch, and info['fell_back'] = 1 when the default was used."""
+    The prediction runs `probe` sweeps first.  If that run fails (half
+    precision overflow, divergence, breakdown) or its contraction rate, fitted
+    on the last third of the probe, cannot reach `tol` within the remaining
+    sweep budget, the default parameters solve from x = 0 instead; otherwise
+    the prediction continues from its own iterate (warm start), so the guard
+    costs one extra launch and no extra sweeps.  Returns (x, info, used) with
+    used in {'mlp', 'default'}; info sums sweeps, inner steps and device
+    seconds over every launch, and info['fell_back'] = 1 when the default was
+    used."""
     a, w = predict(predictor, system, A)
     maxit = kw.pop("maxit_outer", 20000)
     probe = min(probe, maxit)
-    cands = [(a, w, "mlp"), (DEFAULT[0], DEFAULT[1], "default")]
     total = {"outer_sweeps": 0, "inner_H": 0, "inner_S": 0, "seconds": 0.0, "launches": 0}
-    probes = []
-    for al, om, tag in cands:
-        x, info = system.solve(b, al, om, tol=tol, maxit_outer=probe, history=True, **kw)
+
+    def add(info):
         info["launches"] = 1
         for k in total:
             total[k] += info[k]
-        if info["status"] == gadi.OK:
-            info.update(total)
-            info["fell_back"] = int(tag == "default")
-            return x, info, tag
-        hist = system.history
-        proj = _projected_sweeps(hist, tol) if info["status"] == gadi.EMAXIT else math.inf
-        per = info["seconds"] / max(1, info["outer_sweeps"])
-        probes.append((proj * per, al, om, tag, x, hist[-1] if len(hist) else 1.0))
-    # the prediction must beat the default's projection by a margin to be kept
-    pm = next(p for p in probes if p[3] == "mlp")
-    pd = next(p for p in probes if p[3] == "default")
-    _, al, om, tag, x0, res_k = pm if pm[0] < margin * pd[0] else pd
-    x, info = system.solve(b, al, om, tol=tol / max(res_k, 1e-300), x0=x0, maxit_outer=max(0, maxit - probe), **kw)
-    info["launches"] = 1
-    for k in total:
-        total[k] += info[k]
+
+    x, info = system.solve(b, a, w, tol=tol, maxit_outer=probe, history=True, **kw)
+    add(info)
+    if info["status"] == gadi.OK:
+        info.update(total)
+        info["fell_back"] = 0
+        return x, info, "mlp"
+    hist = system.history
+    if info["status"] == gadi.EMAXIT and _projected_sweeps(hist, tol) <= maxit - probe:
+        res_k = hist[-1] if len(hist) else 1.0
+        x, info = system.solve(b, a, w, tol=tol / max(res_k, 1e-300), x0=x, maxit_outer=maxit - probe, **kw)
+        add(info)
+        info.update(total)
+        info["relres"] = info["relres"] * res_k
+        info["fell_back"] = 0
+        return x, info, "mlp"
+    x, info = system.solve(b, DEFAULT[0], DEFAULT[1], tol=tol, maxit_outer=maxit, **kw)
+    add(info)
     info.update(total)
-    info["relres"] = info["relres"] * res_k
-    info["fell_back"] = int(tag == "default")
-    return x, info, tag
+    info["fell_back"] = 1
+    return x, info, "default"

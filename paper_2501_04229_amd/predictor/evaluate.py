@@ -6,10 +6,10 @@ Test systems: gadi_inputs.test_family (3-D convection-diffusion, n ~ U{96..192},
 beta ~ logU(1, 500) on all axes), b = A x* with x* ~ U(-1, 1) seeded per
 system.  Each system is solved with half-precision GADI-IR to RES <= 1e-10
 twice: with the default (0.5, 0.5) and with the predictor's (alpha, omega).
-Reported per system and as geometric means: outer sweeps, work (operator
-products) and device time of the raw prediction, and the device time of
-`solve_auto` (the prediction judged by the default: both probed, the faster
-projection continues from its own iterate).
+Reported per system and as geometric means: outer sweeps, work (phases of the
+solve kernel) and device time of the raw prediction, and the device time of
+`solve_auto` (the prediction guarded by the default: the default replaces it
+only when a short first run fails or stalls).
 """
 from __future__ import annotations
 

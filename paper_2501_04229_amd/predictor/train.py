@@ -39,6 +39,17 @@ def build_family(count):
     return metas, rhs
 
 
+def features_of(metas):
+    """Predictor features of each system, computed by libgadi on the device."""
+    import paper_2501_04229_amd as gadi
+    out = []
+    for A in metas:
+        g = gadi.System(A)
+        out.append(g.features(A.dim, A.grid, A.beta))
+        g.close()
+    return np.stack(out)
+
+
 def load_table(path):
     """Records (list of per-trial dicts per system) and features from a sweep table."""
     d = np.load(path)
@@ -66,10 +77,16 @@ def main():
     ap.add_argument("--table", default=TABLE)
     ap.add_argument("--from-table", action="store_true",
                     help="train from an existing sweep table instead of sweeping again")
+    ap.add_argument("--refeature", action="store_true",
+                    help="with --from-table: recompute the features of the table's systems on the device "
+                         "(after a change of the feature definition) and rewrite the table")
     args = ap.parse_args()
     t0 = time.time()
     if args.from_table:
         recs, feats = load_table(args.table)
+        if args.refeature:
+            metas, _ = build_family(len(recs))
+            feats = features_of(metas)
         t1 = t2 = time.time()
     else:
         metas, rhs = build_family(args.systems)
@@ -83,7 +100,7 @@ def main():
     width = max(len(row) for row in recs)
     table = {k: np.array([[row[t][k] if t < len(row) else np.nan for t in range(width)] for row in recs])
              for k in keys}
-    if not args.from_table:
+    if not args.from_table or args.refeature:
         np.savez(args.table, features=feats, **table)
     pr.save(p, args.out, train_loss=losses, epochs=pr.fit.last["epochs"])
     conv = int(np.nansum(table["status"] == 0))

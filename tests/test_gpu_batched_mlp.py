@@ -147,9 +147,14 @@ def test_mlp_training_fits_and_predicts_in_range():
     p = gadi.Predictor(seed=1)
     losses = p.train(X, Y, epochs=1500, lr=3e-3)
     assert losses[-1] < 0.02 * losses[0]
-    a, w = p.predict(X[0])
+    # alpha = 10^(y0 + (f4 + f5) / 2): the network's output on the alpha_ref scale;
+    # take a sample whose alpha lies inside the clamp range [1e-3, 10]
+    la = Y[:, 0] + 0.5 * (X[:, 4] + X[:, 5])
+    i = int(np.flatnonzero((la > -2.5) & (la < 0.5))[0])
+    a, w = p.predict(X[i])
     assert 1e-3 <= a <= 10.0 and 0.0 <= w <= 1.99
-    assert abs(np.log10(a) - Y[0, 0]) < 0.15 and abs(w - Y[0, 1]) < 0.1
+    y0 = np.log10(a) - 0.5 * (float(X[i, 4]) + float(X[i, 5]))
+    assert abs(y0 - Y[i, 0]) < 0.15 and abs(w - Y[i, 1]) < 0.1
 
 
 def test_mlp_inputs_clamped_to_training_range():
@@ -177,3 +182,47 @@ def test_trained_predictor_stays_in_grid_range():
         g = gadi.System(A)
         a, w = pr.predict(p, g, A)
         assert 1e-3 <= a <= 10.0 and 0.0 <= w <= 1.99
+
+
+def _constant_predictor(y0, omega):
+    """A network whose output is the constant (y0, omega): zero weights, output bias only."""
+    th = np.zeros(4866, np.float32)
+    th[-2] = y0
+    th[-1] = omega
+    p = gadi.Predictor()
+    p.set_weights(th)
+    p.set_norm(np.zeros(8), np.ones(8))
+    return p
+
+
+def test_solve_auto_keeps_a_good_prediction():
+    """The trained predictor on a fresh system: the prediction is kept and the FP64 residual,
+    recomputed by the oracle, meets the tolerance."""
+    from paper_2501_04229_amd import predictor as pr
+    A = gi.convdiff(20, 3, 30.0)
+    g = gadi.System(A)
+    o = oracle.OracleSystem(A)
+    xs, b = gi.rhs_for(A, "uniform", 7)
+    x, info, used = pr.solve_auto(g, A, b, pr.load(), tol=1e-10)
+    assert used == "mlp" and info["fell_back"] == 0 and info["status"] == gadi.OK, info
+    assert np.linalg.norm(b - o.spmv("A", x)) <= 1.0000001e-10 * np.linalg.norm(b)
+    assert info["launches"] >= 1
+
+
+def test_solve_auto_falls_back_when_the_prediction_fails():
+    """alpha clamped to 1e-3 overflows the half-precision S-step on this system: the guard
+    replaces the prediction by the default (0.5, 0.5) from x = 0, which converges."""
+    from paper_2501_04229_amd import predictor as pr
+    A = gi.convdiff(16, 3, 20.0)
+    g = gadi.System(A)
+    o = oracle.OracleSystem(A)
+    xs, b = gi.rhs_for(A, "uniform", 1)
+    p = _constant_predictor(-20.0, 0.5)
+    a, w = pr.predict(p, g, A)
+    assert a == 1e-3 and w == 0.5
+    x, info, used = pr.solve_auto(g, A, b, p, tol=1e-10)
+    assert used == "default" and info["fell_back"] == 1 and info["status"] == gadi.OK, info
+    assert np.linalg.norm(b - o.spmv("A", x)) <= 1.0000001e-10 * np.linalg.norm(b)
+    x1, i1 = g.solve(b, 0.5, 0.5, tol=1e-10)
+    # the default run is the whole solve after the failed probe
+    assert info["outer_sweeps"] - i1["outer_sweeps"] <= 32
