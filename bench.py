@@ -52,6 +52,28 @@ def solve_bytes(prec: str, L: dict, sweeps: int, inner_h: int, inner_s: int, lau
     return float((sweeps + launches) * res + sweeps * upd + inner_h * cg + inner_s * cgne)
 
 
+def profiled_traffic(workload: str, prec: str):
+    """HBM bytes per solve launch from the committed rocprofv3 counter summary of
+    this workload (profiles/solve_kernel_<prec>_<workload>_traffic.md: FETCH_SIZE
+    and WRITE_SIZE runs, copy-calibrated, over the timed launches), or None if
+    there is none or the kernel sources, predictor or workload generator have
+    changed since the counters were taken (source hash mismatch)."""
+    path = os.path.join(ROOT, "profiles", f"solve_kernel_{prec}_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            line = line.strip().strip("`")
+            for key in ("traffic_bytes_per_launch", "source_sha256"):
+                if line.startswith(key + ":"):
+                    vals[key] = line.split(":", 1)[1].strip()
+    from paper_2501_04229_amd.rocprof_summary import source_hash
+    if vals.get("source_sha256") != source_hash(ROOT) or "traffic_bytes_per_launch" not in vals:
+        return None, f"{os.path.relpath(path, ROOT)} is stale (sources changed since the counters were taken)"
+    return float(vals["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+
+
 def load_predictor():
     """The trained (alpha, omega) predictor, or None if no weights are present."""
     if not os.path.exists(WEIGHTS):
@@ -286,6 +308,11 @@ def main():
                      "launch_seconds_mean": float(np.sum(kernel_s)) / launches, "traffic": None},
         "cpu_baseline": cpu,
     }
+    traffic, tsrc = profiled_traffic(args.workload, args.prec)
+    out["roofline"]["traffic"] = traffic
+    out["roofline"]["traffic_source"] = tsrc
+    if traffic:
+        out["roofline"]["traffic_over_algorithmic"] = traffic / nbytes
     if args.copy_calibration:
         xc = torch.ones(1 << 26, device="cuda", dtype=torch.float32)
         yc = torch.empty_like(xc)
