@@ -61,11 +61,20 @@ typedef struct {
  * paper's experiments (Section 4.1 equation) is provided. */
 typedef enum { GADI_SPLIT_HSS = 0 } gadi_splitting;
 
-/* Precision triple (u_r, u, u_f) of Algorithm 1. */
+/* Precision triple (u_r, u, u_f) of Algorithm 1: u_r of the inner solves
+ * (steps 2-3), u of the solution and its update (step 4), u_f of the residual
+ * (step 1).  "half" inner solves store matrices and Krylov vectors in fp16 and
+ * compute in fp32; a single-precision u_f computes the residual with an fp32
+ * copy of A; a single-precision u stores x in fp32.  The last three modes
+ * exist to reproduce the precision study of Section 4.1 (Table 3d); only
+ * gadi_ir_solve accepts them (the batched sweep takes the first three). */
 typedef enum {
-  GADI_PREC_FP64 = 0,    /* u_r = u = u_f = double: plain GADI                  */
-  GADI_PREC_FP16_IR = 1, /* u_r = half (fp16 storage, fp32 arithmetic), u = u_f = double */
-  GADI_PREC_FP32_IR = 2  /* u_r = single, u = u_f = double                      */
+  GADI_PREC_FP64 = 0,    /* (double, double, double): plain GADI               */
+  GADI_PREC_FP16_IR = 1, /* (half, double, double)                              */
+  GADI_PREC_FP32_IR = 2, /* (single, double, double)                            */
+  GADI_PREC_H_D_S = 3,   /* (half, double, single)                              */
+  GADI_PREC_H_S_S = 4,   /* (half, single, single)                              */
+  GADI_PREC_S_S_S = 5    /* (single, single, single)                            */
 } gadi_precision;
 
 typedef struct {

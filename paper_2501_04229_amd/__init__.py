@@ -17,7 +17,7 @@ from . import build as _build
 LIB_PATH = _build.LIB
 
 OK, EINVAL, ENOTSPD, EOVERFLOW16, EDIVERGED, EMAXIT, EHIP, ENOMEM, EBARRIER = range(9)
-PREC = {"fp64": 0, "fp16": 1, "fp32": 2}
+PREC = {"fp64": 0, "fp16": 1, "fp32": 2, "h-d-s": 3, "h-s-s": 4, "s-s-s": 5}
 N_MLP_PARAMS = 4866
 
 

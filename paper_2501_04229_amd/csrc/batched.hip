@@ -89,7 +89,8 @@ __global__ void __launch_bounds__(BLOCK) batched_kernel(BatchArgs ba) {
     a.s_off = S.s_off;
     a.h_diag = S.h_diag;
     a.b = S.b;
-    a.x = (double*)ws;
+    double* const xw = (double*)ws;
+    a.x = xw;
     a.r = ws + vb;
     a.z = ws + 2 * vb;
     a.w = ws + 3 * vb;
@@ -102,7 +103,7 @@ __global__ void __launch_bounds__(BLOCK) batched_kernel(BatchArgs ba) {
     a.eps_s = ba.eps;
     a.hist = nullptr;
     a.prune = ba.best_work ? ba.best_work + si : nullptr;
-    for (int i = threadIdx.x; i < S.npad; i += BLOCK) a.x[i] = 0.0;
+    for (int i = threadIdx.x; i < S.npad; i += BLOCK) xw[i] = 0.0;
     __syncthreads();
     const long long t_start = wall_clock64();
     BlockRed<BLOCK> red;
@@ -115,7 +116,7 @@ __global__ void __launch_bounds__(BLOCK) batched_kernel(BatchArgs ba) {
       ba.info[u] = r;
     }
     if (ti == 0 && S.xoff >= 0)
-      for (int i = threadIdx.x; i < S.n; i += BLOCK) ba.xout[S.xoff + i] = a.x[i];
+      for (int i = threadIdx.x; i < S.n; i += BLOCK) ba.xout[S.xoff + i] = xw[i];
     __syncthreads();
   }
 }

@@ -7,36 +7,63 @@
 
 namespace gadi {
 
-// Precision modes of the inner solves (u_r of Algorithm 1).  MT: stored value
-// type of H and S; VT: stored Krylov vectors; ST: inner solution accumulators;
-// RT: stored outer residual; AT: arithmetic.  The residual r = b - A x and the
-// update x += y always run in double (u_f = u = double).
-struct ModeF16 {
+// Precision modes (u_r, u, u_f) of Algorithm 1.  Inner solves (u_r): MT the
+// stored value type of H and S, VT the stored Krylov vectors, ST the inner
+// solution accumulators, RT the stored outer residual, AT the arithmetic.
+// Outer loop: XT the stored solution x and its update (u), FT the arithmetic
+// of the residual r = b - A x (u_f) and AV the stored values of A it uses.
+struct ModeF16 {  // (half, double, double)
   using MT = __half;
   using VT = __half;
   using ST = float;
   using RT = float;
   using AT = float;
+  using XT = double;
+  using FT = double;
+  using AV = double;
   static constexpr int id = GADI_PREC_FP16_IR;
   static constexpr int tiles = 2;  // tiles per thread with loads in flight together
 };
-struct ModeF32 {
+struct ModeF32 {  // (single, double, double)
   using MT = float;
   using VT = float;
   using ST = float;
   using RT = float;
   using AT = float;
+  using XT = double;
+  using FT = double;
+  using AV = double;
   static constexpr int id = GADI_PREC_FP32_IR;
-  static constexpr int tiles = 2;  // tiles per thread with loads in flight together
+  static constexpr int tiles = 2;
 };
-struct ModeF64 {
+struct ModeF64 {  // (double, double, double): plain GADI
   using MT = double;
   using VT = double;
   using ST = double;
   using RT = double;
   using AT = double;
+  using XT = double;
+  using FT = double;
+  using AV = double;
   static constexpr int id = GADI_PREC_FP64;
-  static constexpr int tiles = 1;  // tiles per thread with loads in flight together
+  static constexpr int tiles = 1;
+};
+struct ModeHDS : ModeF16 {  // (half, double, single)
+  using FT = float;
+  using AV = float;
+  static constexpr int id = GADI_PREC_H_D_S;
+};
+struct ModeHSS : ModeF16 {  // (half, single, single)
+  using XT = float;
+  using FT = float;
+  using AV = float;
+  static constexpr int id = GADI_PREC_H_S_S;
+};
+struct ModeSSS : ModeF32 {  // (single, single, single)
+  using XT = float;
+  using FT = float;
+  using AV = float;
+  static constexpr int id = GADI_PREC_S_S_S;
 };
 
 template <class AT>

@@ -101,6 +101,8 @@ struct System {
   float* h_off32 = nullptr;
   float* s_off32 = nullptr;
   float* h_diag32 = nullptr;
+  float* a_off32 = nullptr;   // fp32 copy of A for single-precision residuals
+  float* a_diag32 = nullptr;
 
   // solver workspace (lazily sized for the widest precision)
   void* ws = nullptr;
@@ -116,9 +118,9 @@ struct System {
   long long* prof = nullptr;  // [20] per-phase profile of the last solve
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // launch shape of the solve kernel per precision mode, chosen by the autotuner
-  int tuned_block[3] = {0, 0, 0};
-  int tuned_per_cu[3] = {0, 0, 0};
-  int tuned_fused[3] = {0, 0, 0};
+  int tuned_block[6] = {0, 0, 0, 0, 0, 0};
+  int tuned_per_cu[6] = {0, 0, 0, 0, 0, 0};
+  int tuned_fused[6] = {0, 0, 0, 0, 0, 0};
   int last_blocks = 0;
   int last_block_threads = 0;
 };

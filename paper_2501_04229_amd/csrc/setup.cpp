@@ -65,7 +65,7 @@ static gadi_status upload(T** dst, const std::vector<T>& src) {
 
 void free_system(System& s) {
   void* ptrs[] = {s.slice_dia, s.dia_off, s.slice_ptr, s.col,     s.a_off,   s.a_diag,  s.h_off64, s.s_off64, s.h_diag64,
-                  s.h_off16,   s.s_off16, s.h_diag16, s.h_off32, s.s_off32, s.h_diag32, s.ws,
+                  s.h_off16,   s.s_off16, s.h_diag16, s.h_off32, s.s_off32, s.h_diag32, s.a_off32, s.a_diag32, s.ws,
                   s.hist,      s.sync,    s.flags,   s.part,    s.result,  s.info, s.prof};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);

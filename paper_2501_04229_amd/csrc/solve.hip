@@ -96,7 +96,8 @@ gadi_status ensure_workspace(System& s) {
   GADI_HIP_CHECK(hipSetDevice(s.device));
   if (s.ws) return GADI_OK;
   // b, x (double) + r, z, w (double-sized) + 8 Krylov vectors (double-sized)
-  s.ws_bytes = (size_t)s.npad * sizeof(double) * 13;
+  // + one double staging vector for a single-precision solution
+  s.ws_bytes = (size_t)s.npad * sizeof(double) * 14;
   GADI_HIP_CHECK(hipMalloc(&s.ws, s.ws_bytes));
   GADI_HIP_CHECK(hipMemset(s.ws, 0, s.ws_bytes));
   GADI_HIP_CHECK(hipMalloc((void**)&s.sync, sizeof(SyncState)));
@@ -124,6 +125,23 @@ static gadi_status ensure_fp32(System& s) {
   hipLaunchKernelGGL(convert_kernel<float>, dim3(1024), dim3(256), 0, s.stream, s.h_diag64, s.h_diag32, (long long)s.npad);
   GADI_HIP_CHECK(hipGetLastError());
   return GADI_OK;
+}
+
+// fp32 copy of A's values for residuals in single precision (u_f = single)
+static gadi_status ensure_a32(System& s) {
+  if (s.a_off32) return GADI_OK;
+  GADI_HIP_CHECK(hipMalloc((void**)&s.a_off32, sizeof(float) * (s.nslots ? s.nslots : 1)));
+  GADI_HIP_CHECK(hipMalloc((void**)&s.a_diag32, sizeof(float) * s.npad));
+  if (s.nslots)
+    hipLaunchKernelGGL(convert_kernel<float>, dim3(1024), dim3(256), 0, s.stream, s.a_off, s.a_off32, (long long)s.nslots);
+  hipLaunchKernelGGL(convert_kernel<float>, dim3(1024), dim3(256), 0, s.stream, s.a_diag, s.a_diag32, (long long)s.npad);
+  GADI_HIP_CHECK(hipGetLastError());
+  return GADI_OK;
+}
+
+__global__ void widen_kernel(const float* __restrict__ in, double* __restrict__ out, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = (double)in[i];
 }
 
 __global__ void fill_zero_kernel(double* __restrict__ p, long long n) {
@@ -157,7 +175,10 @@ static gadi_status launch_t(System& s, SolveArgs a, int per_cu) {
 template <class Mode, bool FUSED, int PW>
 static gadi_status launch_block(System& s, const SolveArgs& a, int block, int per_cu) {
   switch (block) {
-    case 512: return launch_t<Mode, 512, FUSED, PW>(s, a, per_cu);
+    case 512:
+      // the precision-study modes are built in one block size only
+      if constexpr (Mode::id <= GADI_PREC_FP32_IR) return launch_t<Mode, 512, FUSED, PW>(s, a, per_cu);
+      return GADI_EINVAL;
     case 1024: return launch_t<Mode, 1024, FUSED, PW>(s, a, per_cu);
   }
   return GADI_EINVAL;
@@ -174,16 +195,26 @@ static gadi_status launch_mode(System& s, const SolveArgs& a, int block, int per
 
 // fused: Chronopoulos-Gear inner solves (one reduction per CG step) instead of
 // Hestenes-Stiefel (two)
-static gadi_status launch_solve(System& s, int prec, const SolveArgs& a, int block, int per_cu, bool fused) {
-  if (fused) {
-    if (prec == GADI_PREC_FP16_IR) return launch_mode<ModeF16, true>(s, a, block, per_cu);
-    if (prec == GADI_PREC_FP32_IR) return launch_mode<ModeF32, true>(s, a, block, per_cu);
-    return launch_mode<ModeF64, true>(s, a, block, per_cu);
+template <bool FUSED>
+static gadi_status launch_prec(System& s, int prec, const SolveArgs& a, int block, int per_cu) {
+  switch (prec) {
+    case GADI_PREC_FP16_IR: return launch_mode<ModeF16, FUSED>(s, a, block, per_cu);
+    case GADI_PREC_FP32_IR: return launch_mode<ModeF32, FUSED>(s, a, block, per_cu);
+    case GADI_PREC_H_D_S: return launch_mode<ModeHDS, FUSED>(s, a, block, per_cu);
+    case GADI_PREC_H_S_S: return launch_mode<ModeHSS, FUSED>(s, a, block, per_cu);
+    case GADI_PREC_S_S_S: return launch_mode<ModeSSS, FUSED>(s, a, block, per_cu);
   }
-  if (prec == GADI_PREC_FP16_IR) return launch_mode<ModeF16, false>(s, a, block, per_cu);
-  if (prec == GADI_PREC_FP32_IR) return launch_mode<ModeF32, false>(s, a, block, per_cu);
-  return launch_mode<ModeF64, false>(s, a, block, per_cu);
+  return launch_mode<ModeF64, FUSED>(s, a, block, per_cu);
 }
+
+static gadi_status launch_solve(System& s, int prec, const SolveArgs& a, int block, int per_cu, bool fused) {
+  return fused ? launch_prec<true>(s, prec, a, block, per_cu) : launch_prec<false>(s, prec, a, block, per_cu);
+}
+
+// solution stored in single precision (u = single)
+static bool single_solution(int prec) { return prec == GADI_PREC_H_S_S || prec == GADI_PREC_S_S_S; }
+// residual in single precision (u_f = single)
+static bool single_residual(int prec) { return prec >= GADI_PREC_H_D_S; }
 
 // Autotuner: time three outer sweeps from x = 0 in every candidate (threads
 // per block x blocks per compute unit x inner-solver variant), after one
@@ -269,14 +300,16 @@ extern "C" gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x,
   gadi_options o;
   if (opts) o = *opts;
   else gadi_default_options(&o, GADI_PREC_FP16_IR);
-  if (o.prec < GADI_PREC_FP64 || o.prec > GADI_PREC_FP32_IR || !(o.eps_inner > 0.0) || o.eps_inner >= 1.0 ||
+  if (o.prec < GADI_PREC_FP64 || o.prec > GADI_PREC_S_S_S || !(o.eps_inner > 0.0) || o.eps_inner >= 1.0 ||
       o.maxit_outer < 0 || o.maxit_inner < 1)
     return GADI_EINVAL;
   System& s = h->sys;
   gadi_status st;
   if ((st = device_props()) != GADI_OK) return st;
   if ((st = ensure_workspace(s)) != GADI_OK) return st;
-  if (o.prec == GADI_PREC_FP32_IR && (st = ensure_fp32(s)) != GADI_OK) return st;
+  const bool inner32 = o.prec == GADI_PREC_FP32_IR || o.prec == GADI_PREC_S_S_S;
+  if (inner32 && (st = ensure_fp32(s)) != GADI_OK) return st;
+  if (single_residual(o.prec) && (st = ensure_a32(s)) != GADI_OK) return st;
   if (o.record_history) {
     int cap = o.maxit_outer + 1;
     if (cap > s.hist_cap) {
@@ -307,8 +340,8 @@ extern "C" gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x,
   a.slice_dia = s.slice_dia;
   a.dia_off = s.dia_off;
   for (int j = 0; j < kDiaMax; ++j) a.dia_u[j] = s.dia_u[j];
-  a.a_off = s.a_off;
-  a.a_diag = s.a_diag;
+  a.a_off = single_residual(o.prec) ? (const void*)s.a_off32 : (const void*)s.a_off;
+  a.a_diag = single_residual(o.prec) ? (const void*)s.a_diag32 : (const void*)s.a_diag;
   a.b = db;
   a.x = dx;
   a.r = vbase;
@@ -328,11 +361,11 @@ extern "C" gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x,
   a.hist = o.record_history ? s.hist : nullptr;
   a.timeout = barrier_timeout_ticks();
   a.prof = s.prof;
-  if (o.prec == GADI_PREC_FP16_IR) {
+  if (o.prec == GADI_PREC_FP16_IR || o.prec == GADI_PREC_H_D_S || o.prec == GADI_PREC_H_S_S) {
     a.h_off = s.h_off16;
     a.s_off = s.s_off16;
     a.h_diag = s.h_diag16;
-  } else if (o.prec == GADI_PREC_FP32_IR) {
+  } else if (inner32) {
     a.h_off = s.h_off32;
     a.s_off = s.s_off32;
     a.h_diag = s.h_diag32;
@@ -342,12 +375,25 @@ extern "C" gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x,
     a.h_diag = s.h_diag64;
   }
   if ((st = tune_solve(s, o.prec, a, dx)) != GADI_OK) return st;
-  GADI_HIP_CHECK(hipMemcpyAsync(dx, x, sizeof(double) * s.n, kin, s.stream));
+  // a single-precision solution lives in dx as floats; the caller's doubles
+  // pass through the staging vector after the Krylov vectors
+  double* stage = (double*)(vbase + 11 * vbytes);
+  const bool xs = single_solution(o.prec);
+  GADI_HIP_CHECK(hipMemcpyAsync(xs ? stage : dx, x, sizeof(double) * s.n, kin, s.stream));
+  if (xs) {
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(256), dim3(256), 0, s.stream, dx, (long long)s.npad);
+    hipLaunchKernelGGL(convert_kernel<float>, dim3(1024), dim3(256), 0, s.stream, stage, (float*)dx, (long long)s.n);
+    GADI_HIP_CHECK(hipGetLastError());
+  }
   GADI_HIP_CHECK(hipEventRecord(s.ev0, s.stream));
   st = launch_solve(s, o.prec, a, s.tuned_block[o.prec], s.tuned_per_cu[o.prec], s.tuned_fused[o.prec] != 0);
   if (st != GADI_OK) return st;
   GADI_HIP_CHECK(hipEventRecord(s.ev1, s.stream));
-  GADI_HIP_CHECK(hipMemcpyAsync(x, dx, sizeof(double) * s.n, kout, s.stream));
+  if (xs) {
+    hipLaunchKernelGGL(widen_kernel, dim3(1024), dim3(256), 0, s.stream, (const float*)dx, stage, (long long)s.n);
+    GADI_HIP_CHECK(hipGetLastError());
+  }
+  GADI_HIP_CHECK(hipMemcpyAsync(x, xs ? stage : dx, sizeof(double) * s.n, kout, s.stream));
   DevInfo di;
   GADI_HIP_CHECK(hipMemcpyAsync(&di, s.info, sizeof(DevInfo), hipMemcpyDeviceToHost, s.stream));
   GADI_HIP_CHECK(hipStreamSynchronize(s.stream));

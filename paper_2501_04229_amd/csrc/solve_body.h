@@ -36,13 +36,13 @@ struct SolveArgs {
   // column offsets shared by every slice when the layout is uniformly
   // diagonal-style (System::dia_uniform slots per slice), else unused
   int32_t dia_u[kDiaMax];
-  const double* a_off;
-  const double* a_diag;
+  const void* a_off;   // Mode::AV values of A on the pattern
+  const void* a_diag;  // Mode::AV diagonal of A
   const void* h_off;
   const void* s_off;
   const void* h_diag;
   const double* b;
-  double* x;
+  void* x;  // Mode::XT solution
   void* r;
   void* z;
   void* w;
@@ -323,7 +323,12 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
   VT* const S1 = (VT*)a.v[5];
   VT* __restrict__ P = (VT*)a.v[6];
   VT* __restrict__ T = (VT*)a.v[7];
-  double* __restrict__ x = a.x;
+  using XT = typename Mode::XT;
+  using FT = typename Mode::FT;
+  using AV = typename Mode::AV;
+  XT* __restrict__ x = (XT*)a.x;
+  const AV* __restrict__ aoff = (const AV*)a.a_off;
+  const AV* __restrict__ adiag = (const AV*)a.a_diag;
   const double* __restrict__ b = a.b;
 
   const AT alpha = (AT)a.alpha;
@@ -361,14 +366,17 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
           t0, t1,
           [&](unsigned row) {
             struct {
-              double d, xr, br;
-              decltype(pat.gather(0u, a.a_off, gx)) g;
-            } l{at(a.a_diag, row), at(x, row), at(b, row), pat.gather(row, a.a_off, gx)};
+              AV d;
+              XT xr;
+              double br;
+              decltype(pat.gather(0u, aoff, gx)) g;
+            } l{at(adiag, row), at(x, row), at(b, row), pat.gather(row, aoff, gx)};
             return l;
           },
           [&](const auto& l) {
-            const double ax = l.d * l.xr + pat.template dot<double>(l.g, [](double v) { return v; });
-            return l.br - ax;
+            // in the residual precision u_f (double unless a single-precision mode)
+            const FT ax = (FT)l.d * (FT)l.xr + pat.template dot<FT>(l.g, [](XT v) { return (FT)v; });
+            return (double)((FT)l.br - ax);
           },
           [&](unsigned row, double ri) {
             at(r, row) = (RT)ri;
@@ -990,16 +998,17 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
             [&](unsigned row) {
               struct {
                 ST w;
-                double x;
+                XT x;
                 decltype(pat.gather(0u, soff, gw)) g;
               } l{at(wsol, row), at(x, row), pat.gather(row, soff, gw)};
               return l;
             },
             [&](const auto& l) {
               const AT ui = (AT)l.w - inv_alpha * pat.template dot<AT>(l.g, [](ST v) { return (AT)v; });
-              return l.x + (double)ui * unscale;
+              // the update in the solution precision u
+              return (XT)(l.x + (XT)((double)ui * unscale));
             },
-            [&](unsigned row, double xn) { at(x, row) = xn; });
+            [&](unsigned row, XT xn) { at(x, row) = xn; });
         ALLREDUCE_P(8, 0.0, 0.0, 0.0, 0.0);
       }
     }
