@@ -151,7 +151,8 @@ class System:
         self.history = None
 
     def close(self):
-        if getattr(self, "_h", None):
+        # at interpreter exit the module globals may already be gone: nothing to free then
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.gadi_destroy(self._h)
             self._h = None
 
@@ -290,7 +291,7 @@ class Predictor:
         self._h = h
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.gadi_mlp_destroy(self._h)
             self._h = None
 

@@ -3,42 +3,88 @@
 #include <cmath>
 #include <vector>
 
-#include "device_common.h"
+#include "solve_body.h"
 
 namespace gadi {
 
+// The products run the solver's row loop (solve_body.h): every load of U
+// tiles of BLOCK rows is issued before their arithmetic, under the same
+// pattern policies (uniform diagonal layout: offsets in scalar registers).
+// A block owns U consecutive tiles (an XCD-contiguous remap of the blocks,
+// as in the solver, measured slower here at 256^3).  x has the caller's
+// length n: rows past
+// n read no x (their diagonal term is zero) and write no y.
+constexpr int kSpmvBlock = 256;
+
 // y = A x in double (the residual's operator, step 1 of Algorithm 1)
-__global__ void __launch_bounds__(kRowBlock) spmv_a64_kernel(const int32_t* __restrict__ sp, const int32_t* __restrict__ col,
-    const int32_t* __restrict__ dia, const int32_t* __restrict__ doff,
-                                                           const double* __restrict__ off, const double* __restrict__ diag,
-                                                           const double* __restrict__ x, double* __restrict__ y, int n) {
-  const int row = blockIdx.x * kRowBlock + threadIdx.x;
-  const double xi = row < n ? x[row] : 0.0;
-  const double acc = diag[row] * xi + row_sum<double>(row, Pattern{sp, col, dia, doff, n - 1}, off, [&](int c) { return x[c]; });
-  if (row < n) y[row] = acc;
+template <int U, class Pat>
+__global__ void __launch_bounds__(kSpmvBlock) spmv_a64_kernel(Pat pat, const double* __restrict__ off,
+                                                             const double* __restrict__ diag,
+                                                             const double* __restrict__ x, double* __restrict__ y,
+                                                             int n, int ntiles) {
+  const int t0 = blockIdx.x * U, t1 = t0 + U < ntiles ? t0 + U : ntiles;
+  auto gx = [&](unsigned c) { return at(x, c); };
+  for_rows<kSpmvBlock, U>(
+      t0, t1,
+      [&](unsigned row) {
+        struct {
+          double d, xr;
+          decltype(pat.gather(0u, off, gx)) g;
+        } l{at(diag, row), row < (unsigned)n ? at(x, row) : 0.0, pat.gather(row, off, gx)};
+        return l;
+      },
+      [&](const auto& l) { return l.d * l.xr + pat.template dot<double>(l.g, [](double v) { return v; }); },
+      [&](unsigned row, double v) {
+        if (row < (unsigned)n) at(y, row) = v;
+      });
 }
 
 // y = (alpha I + H) x with H, x, y in the value type MT, arithmetic in AT
-template <class MT, class AT>
-__global__ void __launch_bounds__(kRowBlock) spmv_h_kernel(const int32_t* __restrict__ sp, const int32_t* __restrict__ col,
-    const int32_t* __restrict__ dia, const int32_t* __restrict__ doff,
-                                                         const MT* __restrict__ off, const MT* __restrict__ diag,
-                                                         const MT* __restrict__ x, MT* __restrict__ y, AT alpha, int n) {
-  const int row = blockIdx.x * kRowBlock + threadIdx.x;
-  const AT xi = row < n ? ld<AT>(x[row]) : AT(0);
-  const AT acc = (alpha + ld<AT>(diag[row])) * xi + row_sum<AT>(row, Pattern{sp, col, dia, doff, n - 1}, off, [&](int c) { return ld<AT>(x[c]); });
-  if (row < n) y[row] = st<MT>(acc);
+template <int U, class Pat, class MT, class AT>
+__global__ void __launch_bounds__(kSpmvBlock) spmv_h_kernel(Pat pat, const MT* __restrict__ off,
+                                                           const MT* __restrict__ diag, const MT* __restrict__ x,
+                                                           MT* __restrict__ y, AT alpha, int n, int ntiles) {
+  const int t0 = blockIdx.x * U, t1 = t0 + U < ntiles ? t0 + U : ntiles;
+  auto gx = [&](unsigned c) { return at(x, c); };
+  for_rows<kSpmvBlock, U>(
+      t0, t1,
+      [&](unsigned row) {
+        struct {
+          MT d, xr;
+          decltype(pat.gather(0u, off, gx)) g;
+        } l{at(diag, row), row < (unsigned)n ? at(x, row) : MT(0), pat.gather(row, off, gx)};
+        return l;
+      },
+      [&](const auto& l) {
+        return (alpha + ld<AT>(l.d)) * ld<AT>(l.xr) + pat.template dot<AT>(l.g, [](MT v) { return ld<AT>(v); });
+      },
+      [&](unsigned row, AT v) {
+        if (row < (unsigned)n) at(y, row) = st<MT>(v);
+      });
 }
 
 // y = (I + S / alpha) x, half in/out, float arithmetic
-__global__ void __launch_bounds__(kRowBlock) spmv_s16_kernel(const int32_t* __restrict__ sp, const int32_t* __restrict__ col,
-    const int32_t* __restrict__ dia, const int32_t* __restrict__ doff,
-                                                           const __half* __restrict__ off, const __half* __restrict__ x,
-                                                           __half* __restrict__ y, float inv_alpha, int n) {
-  const int row = blockIdx.x * kRowBlock + threadIdx.x;
-  const float xi = row < n ? __half2float(x[row]) : 0.f;
-  const float acc = xi + inv_alpha * row_sum<float>(row, Pattern{sp, col, dia, doff, n - 1}, off, [&](int c) { return __half2float(x[c]); });
-  if (row < n) y[row] = __float2half_rn(acc);
+template <int U, class Pat>
+__global__ void __launch_bounds__(kSpmvBlock) spmv_s16_kernel(Pat pat, const __half* __restrict__ off,
+                                                             const __half* __restrict__ x, __half* __restrict__ y,
+                                                             float inv_alpha, int n, int ntiles) {
+  const int t0 = blockIdx.x * U, t1 = t0 + U < ntiles ? t0 + U : ntiles;
+  auto gx = [&](unsigned c) { return at(x, c); };
+  for_rows<kSpmvBlock, U>(
+      t0, t1,
+      [&](unsigned row) {
+        struct {
+          __half xr;
+          decltype(pat.gather(0u, off, gx)) g;
+        } l{row < (unsigned)n ? at(x, row) : __half(0.f), pat.gather(row, off, gx)};
+        return l;
+      },
+      [&](const auto& l) {
+        return __half2float(l.xr) + inv_alpha * pat.template dot<float>(l.g, [](__half v) { return __half2float(v); });
+      },
+      [&](unsigned row, float v) {
+        if (row < (unsigned)n) at(y, row) = __float2half_rn(v);
+      });
 }
 
 // Per-block Gershgorin extrema: [min(H_ii - R^H_i), max(H_ii + R^H_i), max R^S_i, min R^S_i]
@@ -88,29 +134,50 @@ __global__ void __launch_bounds__(kRowBlock) gershgorin_kernel(const int32_t* __
 
 using namespace gadi;
 
+// U16 / U64: tiles per block of the half and double products
+template <int U16, int U64, class Pat>
+static void launch_products(System& s, const Pat& pat, int which, double alpha, const void* x, void* y) {
+  const int ntiles = s.npad / kSpmvBlock;
+  const dim3 g16((ntiles + U16 - 1) / U16), g64((ntiles + U64 - 1) / U64), block(kSpmvBlock);
+  switch (which) {
+    case 0:
+      hipLaunchKernelGGL((spmv_a64_kernel<U64, Pat>), g64, block, 0, s.stream, pat, s.a_off, s.a_diag,
+                         (const double*)x, (double*)y, s.n, ntiles);
+      break;
+    case 1:
+      hipLaunchKernelGGL((spmv_h_kernel<U16, Pat, __half, float>), g16, block, 0, s.stream, pat, s.h_off16,
+                         s.h_diag16, (const __half*)x, (__half*)y, (float)alpha, s.n, ntiles);
+      break;
+    case 2:
+      hipLaunchKernelGGL((spmv_s16_kernel<U16, Pat>), g16, block, 0, s.stream, pat, s.s_off16, (const __half*)x,
+                         (__half*)y, (float)(1.0 / alpha), s.n, ntiles);
+      break;
+    case 3:
+      hipLaunchKernelGGL((spmv_h_kernel<U64, Pat, double, double>), g64, block, 0, s.stream, pat, s.h_off64,
+                         s.h_diag64, (const double*)x, (double*)y, alpha, s.n, ntiles);
+      break;
+  }
+}
+
+template <int W>
+static PatDia<W> uniform_pattern(const System& s) {
+  PatDia<W> p;
+  for (int j = 0; j < W; ++j) p.off[j] = s.dia_u[j];
+  p.nmax = s.n - 1;
+  return p;
+}
+
 extern "C" gadi_status gadi_spmv(gadi_handle* h, int32_t which, double alpha, const void* x, void* y) {
   if (!h || !x || !y || which < 0 || which > 3) return GADI_EINVAL;
   if ((which == 1 || which == 2 || which == 3) && !(alpha > 0.0)) return GADI_EINVAL;
   System& s = h->sys;
   GADI_HIP_CHECK(hipSetDevice(s.device));
-  const dim3 grid(s.npad / kRowBlock), block(kRowBlock);
-  switch (which) {
-    case 0:
-      hipLaunchKernelGGL(spmv_a64_kernel, grid, block, 0, s.stream, s.slice_ptr, s.col, s.slice_dia, s.dia_off, s.a_off, s.a_diag,
-                         (const double*)x, (double*)y, s.n);
-      break;
-    case 1:
-      hipLaunchKernelGGL((spmv_h_kernel<__half, float>), grid, block, 0, s.stream, s.slice_ptr, s.col, s.slice_dia, s.dia_off, s.h_off16,
-                         s.h_diag16, (const __half*)x, (__half*)y, (float)alpha, s.n);
-      break;
-    case 2:
-      hipLaunchKernelGGL(spmv_s16_kernel, grid, block, 0, s.stream, s.slice_ptr, s.col, s.slice_dia, s.dia_off, s.s_off16, (const __half*)x,
-                         (__half*)y, (float)(1.0 / alpha), s.n);
-      break;
-    case 3:
-      hipLaunchKernelGGL((spmv_h_kernel<double, double>), grid, block, 0, s.stream, s.slice_ptr, s.col, s.slice_dia, s.dia_off, s.h_off64,
-                         s.h_diag64, (const double*)x, (double*)y, alpha, s.n);
-      break;
+  switch (s.dia_uniform) {
+    case 4: launch_products<4, 2>(s, uniform_pattern<4>(s), which, alpha, x, y); break;
+    case 6: launch_products<4, 2>(s, uniform_pattern<6>(s), which, alpha, x, y); break;
+    default:
+      launch_products<1, 1>(s, PatGeneric{Pattern{s.slice_ptr, s.col, s.slice_dia, s.dia_off, s.n - 1}}, which, alpha,
+                         x, y);
   }
   GADI_HIP_CHECK(hipGetLastError());
   return GADI_OK;
