@@ -20,3 +20,4 @@ from .convdiff import (  # noqa: F401
     ALPHA_GRID,
     OMEGA_GRID,
 )
+from .sylvester import paper_tridiag, random_tridiag, sylvester_rhs  # noqa: F401

@@ -239,6 +239,38 @@ gadi_status gadi_get_layout(gadi_handle* h, int64_t* out);
  * variables GADI_SOLVE_BLOCK and GADI_BLOCKS_PER_CU). */
 int32_t gadi_solver_blocks(gadi_handle* h, int32_t* threads);
 
+/* ------------------------------------------------------------------------
+ * GADI-AB for the continuous Sylvester equation A X + X B = C (Section 4.3):
+ * GADI with L(X) = A X + X B split into M(X) = A X and N(X) = X B.  One sweep:
+ *   R = C - A X - X B                      (double)
+ *   (alpha I + A) Z = R                    (one tridiagonal solve per column)
+ *   Y (alpha I + B) = (2 - omega) alpha Z  (one tridiagonal solve per row)
+ *   X <- X + Y                             (double)
+ * The inner solves run in the precision prec selects (GADI_PREC_FP64,
+ * GADI_PREC_FP32_IR or GADI_PREC_FP16_IR: right-hand sides scaled by a power
+ * of two and rounded to half, A and B rounded to half, fp32 arithmetic); each
+ * is exact up to rounding (LU factors shared by all columns / rows, the
+ * recurrences split into chunks of rows that are joined by their boundary
+ * values).  Residual and update are in double. */
+typedef struct gadi_sylv gadi_sylv;
+
+/* A (m x m) and B (n x n) tridiagonal, host arrays: sub[k-1], diag[k],
+ * sup[k-1] with T[i+1][i] = sub[i] and T[i][i+1] = sup[i] (copied).  EINVAL
+ * for m or n outside [1, 2^15] or missing arrays. */
+gadi_status gadi_sylv_setup(int32_t m, int32_t n, const double* a_sub, const double* a_diag, const double* a_sup,
+                            const double* b_sub, const double* b_diag, const double* b_sup, gadi_sylv** out);
+/* Solve from X (in: X_0, out: the last iterate) until ||R||_F <= tol ||R_0||_F.
+ * C and X are m x n row-major doubles, host or device pointers per
+ * opts->on_device; opts->prec, eps_inner (unused: the inner solves are direct),
+ * maxit_outer, record_history apply.  info: sweeps, relres, device seconds;
+ * inner_H / inner_S count the column and row solves.  Status as gadi_ir_solve. */
+gadi_status gadi_sylv_solve(gadi_sylv* h, const double* C, double* X, double alpha, double omega, double tol,
+                            const gadi_options* opts, gadi_solve_info* info);
+/* RES per sweep of the last solve with record_history (as gadi_get_history). */
+int32_t gadi_sylv_get_history(gadi_sylv* h, double* out, int32_t cap);
+gadi_status gadi_sylv_set_stream(gadi_sylv* h, void* hip_stream);
+gadi_status gadi_sylv_destroy(gadi_sylv* h);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,6 +82,11 @@ def _load():
         "gadi_status_str": (ctypes.c_char_p, [i32]),
         "gadi_solver_blocks": (i32, [vp, P(i32)]),
         "gadi_default_options": (None, [P(_Options), ctypes.c_int]),
+        "gadi_sylv_setup": (i32, [i32, i32, vp, vp, vp, vp, vp, vp, P(vp)]),
+        "gadi_sylv_solve": (i32, [vp, vp, vp, f64, f64, f64, P(_Options), P(SolveInfo)]),
+        "gadi_sylv_get_history": (i32, [vp, P(f64), i32]),
+        "gadi_sylv_set_stream": (i32, [vp, vp]),
+        "gadi_sylv_destroy": (i32, [vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -367,3 +372,61 @@ class Predictor:
         _check(_lib.gadi_predict_params(self._h, ctypes.c_void_p(f.ctypes.data), ctypes.byref(a), ctypes.byref(w)),
                "gadi_predict_params")
         return a.value, w.value
+
+
+class Sylvester:
+    """GADI-AB for the continuous Sylvester equation A X + X B = C (libgadi's
+    gadi_sylv_*).  A (m x m) and B (n x n) are tridiagonal triples
+    (sub[k-1], diag[k], sup[k-1]) of float64 arrays, T[i+1, i] = sub[i]."""
+
+    def __init__(self, A, B):
+        a = [np.ascontiguousarray(v, dtype=np.float64) for v in A]
+        b = [np.ascontiguousarray(v, dtype=np.float64) for v in B]
+        self.m, self.n = len(a[1]), len(b[1])
+        h = ctypes.c_void_p()
+        ptr = lambda v: ctypes.c_void_p(v.ctypes.data) if v.size else None
+        _check(_lib.gadi_sylv_setup(self.m, self.n, ptr(a[0]), ptr(a[1]), ptr(a[2]), ptr(b[0]), ptr(b[1]), ptr(b[2]),
+                                    ctypes.byref(h)), "gadi_sylv_setup")
+        self._h = h
+        self.history = np.zeros(0)
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.gadi_sylv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def solve(self, C, alpha=0.5, omega=0.5, tol=1e-10, x0=None, prec="fp16", maxit_outer=20000, history=False):
+        """C (and x0) as (m, n) numpy float64 (host) or torch float64 CUDA tensors.
+        prec in {'fp64', 'fp32', 'fp16'}.  Returns (X, info-dict)."""
+        if prec not in ("fp64", "fp32", "fp16"):
+            raise ValueError("GADI-AB runs its inner solves in fp64, fp32 or fp16")
+        dev = _is_device_tensor(C)
+        if dev:
+            import torch
+            _check(_lib.gadi_sylv_set_stream(self._h, _current_stream()), "gadi_sylv_set_stream")
+            C = C.contiguous()
+            X = torch.zeros_like(C) if x0 is None else x0.clone().contiguous()
+            cp, xp = C.data_ptr(), X.data_ptr()
+        else:
+            _check(_lib.gadi_sylv_set_stream(self._h, None), "gadi_sylv_set_stream")
+            C = np.ascontiguousarray(C, dtype=np.float64)
+            X = np.zeros_like(C) if x0 is None else np.array(x0, dtype=np.float64, copy=True, order="C")
+            cp, xp = C.ctypes.data, X.ctypes.data
+        if tuple(C.shape) != (self.m, self.n) or tuple(X.shape) != (self.m, self.n):
+            raise ValueError("C and x0 must be m x n")
+        o = options(prec, None, maxit_outer, 1, dev, history)
+        info = SolveInfo()
+        st = _lib.gadi_sylv_solve(self._h, ctypes.c_void_p(cp), ctypes.c_void_p(xp), float(alpha), float(omega),
+                                  float(tol), ctypes.byref(o), ctypes.byref(info))
+        if st not in (OK, EMAXIT, EDIVERGED, EOVERFLOW16):
+            _check(st, "gadi_sylv_solve")
+        if history:
+            buf = np.zeros(maxit_outer + 1)
+            k = _lib.gadi_sylv_get_history(self._h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(buf))
+            self.history = buf[:k]
+        d = info.as_dict()
+        d["status_str"] = status_str(st)
+        return X, d

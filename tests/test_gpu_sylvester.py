@@ -1,0 +1,125 @@
+"""GPU parity of GADI-AB (Section 4.3, A X + X B = C) against the float64 oracle.
+
+- FP64 inner solves: the same algorithm in the same precision as the oracle, so
+  sweep counts agree within 1 and the iterates agree closely;
+- FP32 / FP16 inner solves: the FP64 residual of the result, recomputed by the
+  oracle on the CPU, meets the tolerance, and the error against the exact
+  solution (Bartels-Stewart or the manufactured one) obeys the forward bound
+  ||X - X*||_F <= ||R||_F / lambda_min(sym(L)), lambda_min(sym(L)) =
+  lambda_min((A + A^T)/2) + lambda_min((B + B^T)/2) for L = I (x) A + B^T (x) I;
+- shapes with ragged chunks (64-row chunks), single rows and columns, non-square;
+- argument checks and device pointers.
+"""
+import numpy as np
+import pytest
+
+import gadi_inputs as gi
+from oracle import sylvester as osyl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2501_04229_amd as gadi  # noqa: E402
+
+CASES = [
+    ("paper64_r0.1", lambda: (gi.paper_tridiag(64, 0.1), gi.paper_tridiag(64, 0.1))),
+    ("rand100x77", lambda: (gi.random_tridiag(100, 1), gi.random_tridiag(77, 2))),
+    ("rand130x200", lambda: (gi.random_tridiag(130, 3), gi.random_tridiag(200, 4))),
+    ("rand1x5", lambda: (gi.random_tridiag(1, 5), gi.random_tridiag(5, 6))),
+    ("rand5x1", lambda: (gi.random_tridiag(5, 7), gi.random_tridiag(1, 8))),
+    ("paper257_r1", lambda: (gi.paper_tridiag(257, 1.0), gi.paper_tridiag(257, 1.0))),
+]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=[c[0] for c in CASES])
+def case(request):
+    A, B = request.param[1]()
+    Xs, C = gi.sylvester_rhs(A, B, "uniform", 11)
+    return A, B, Xs, C, gadi.Sylvester(A, B)
+
+
+def lam_min_sym(T):
+    D = osyl.dense(T)
+    return float(np.linalg.eigvalsh((D + D.T) / 2.0)[0])
+
+
+def _relres(A, B, C, X):
+    return float(np.linalg.norm(osyl.residual(A, B, C, X)) / np.linalg.norm(C))
+
+
+def test_fp64_follows_the_oracle(case):
+    A, B, Xs, C, g = case
+    ref = osyl.gadi_ab(A, B, C, 0.5, 0.5, tol=1e-12, maxit=5000)
+    X, info = g.solve(C, 0.5, 0.5, tol=1e-12, prec="fp64", maxit_outer=5000)
+    assert info["status"] == gadi.OK, info
+    assert abs(info["outer_sweeps"] - ref["sweeps"]) <= 1, (info, ref["sweeps"])
+    assert _relres(A, B, C, X) <= 1.0000001e-12
+    assert np.linalg.norm(X - ref["x"]) <= 1e-10 * np.linalg.norm(ref["x"])
+
+
+def test_fp64_iterates_match_sweep_by_sweep(case):
+    A, B, Xs, C, g = case
+    for k in (1, 2, 5):
+        ref = osyl.gadi_ab(A, B, C, 0.7, 0.3, tol=0.0, maxit=k)
+        X, info = g.solve(C, 0.7, 0.3, tol=0.0, prec="fp64", maxit_outer=k)
+        assert info["outer_sweeps"] == k
+        assert np.linalg.norm(X - ref["x"]) <= 1e-13 * max(1.0, np.linalg.norm(ref["x"]))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_low_precision_inner_solves_reach_the_double_residual(case, prec):
+    A, B, Xs, C, g = case
+    X, info = g.solve(C, 0.5, 0.5, tol=1e-10, prec=prec, maxit_outer=5000, history=True)
+    assert info["status"] == gadi.OK, info
+    rel = _relres(A, B, C, X)
+    assert rel <= 1.0000001e-10, rel
+    lmin = lam_min_sym(A) + lam_min_sym(B)
+    assert lmin > 0
+    R = osyl.residual(A, B, C, X)
+    assert np.linalg.norm(X - Xs) <= np.linalg.norm(R) / lmin * 1.0000001 + 1e-12 * np.linalg.norm(Xs)
+    h = g.history
+    assert len(h) == info["outer_sweeps"] + 1 and h[0] == 1.0 and h[-1] <= 1e-10
+
+
+def test_fixed_point_is_the_bartels_stewart_solution():
+    import scipy.linalg as sla
+    A, B = gi.random_tridiag(40, 21), gi.random_tridiag(33, 22)
+    C = np.random.default_rng(23).normal(size=(40, 33))
+    g = gadi.Sylvester(A, B)
+    X, info = g.solve(C, 1.0, 0.5, tol=1e-12, prec="fp16", maxit_outer=5000)
+    assert info["status"] == gadi.OK
+    Xref = sla.solve_sylvester(osyl.dense(A), osyl.dense(B), C)
+    assert np.linalg.norm(X - Xref) <= 1e-9 * np.linalg.norm(Xref)
+
+
+def test_device_tensors_and_warm_start():
+    A, B = gi.paper_tridiag(96, 0.01), gi.paper_tridiag(96, 0.01)
+    Xs, C = gi.sylvester_rhs(A, B, "ones")
+    g = gadi.Sylvester(A, B)
+    Cd = torch.from_numpy(C).cuda()
+    X1, i1 = g.solve(Cd, 0.5, 0.5, tol=1e-12, prec="fp16", maxit_outer=10)
+    assert i1["status"] == gadi.EMAXIT and i1["outer_sweeps"] == 10
+    X2, i2 = g.solve(Cd, 0.5, 0.5, tol=1e-12, prec="fp16", x0=X1)
+    assert i2["status"] == gadi.OK
+    Xh = X2.cpu().numpy()
+    assert _relres(A, B, C, Xh) <= 1e-10 * np.linalg.norm(osyl.residual(A, B, C, X1.cpu().numpy())) / np.linalg.norm(C) * 1.0000001
+
+
+def test_argument_checks():
+    A = gi.paper_tridiag(8, 0.1)
+    g = gadi.Sylvester(A, A)
+    C = np.ones((8, 8))
+    for kw in ({"alpha": 0.0}, {"omega": 2.0}, {"tol": -1.0}):
+        args = {"alpha": 0.5, "omega": 0.5, "tol": 1e-10}
+        args.update(kw)
+        with pytest.raises(gadi.GadiError):
+            g.solve(C, **args)
+    with pytest.raises(ValueError):
+        g.solve(np.ones((8, 7)))
+    with pytest.raises(ValueError):
+        g.solve(C, prec="h-d-s")
+    with pytest.raises(gadi.GadiError):
+        gadi.Sylvester((np.zeros(0), np.zeros(0), np.zeros(0)), A)
