@@ -15,9 +15,10 @@
 // z_i = z^_i + y_{s-1} q_i + z_e h_i, where f, q, h depend on the matrix only
 // (precomputed).  A short chain per column then fixes the chunk boundary
 // values y_{s-1} (forward) and z_e (backward).  Kernels per sweep:
-//   residual (double) -> partial sums -> column chunks -> column chains ->
-//   column correction (writes G, tracks max |G|) -> row chunks (LDS tiles)
-//   -> row chains -> row correction fused with the update of X (double).
+//   residual (double) -> partial sums and stopping test -> column chunks ->
+//   column chains (also bound max |G|) -> row chunks, which apply the column
+//   correction and form G while staging LDS tiles -> row chains -> row
+//   correction fused with the update of X (double).
 // X, C and the work arrays are m x n row-major.
 #include <cmath>
 #include <cstdio>
@@ -30,6 +31,8 @@ namespace gadi {
 constexpr int kChunk = 64;         // rows of a chunk of the recurrences
 constexpr int kSylBlock = 256;     // threads of the elementwise kernels
 constexpr int kSylMax = 1 << 15;   // largest m or n
+constexpr int kRowsPer = 16;       // rows per block of the residual and update kernels
+static_assert(kChunk == 64, "the row tiles of the row solves are one column chunk high");
 
 // Coefficients of one direction's solves (device, inner type IT): per row i
 // of the (alpha I + T) system: l_i, 1/p_i, sup_i, f_i, q_i, h_i.
@@ -41,6 +44,8 @@ struct Factors {
   const IT* f;
   const IT* q;
   const IT* h;
+  const IT* qm;  // per chunk: max |q_i|, max |h_i| over the chunk's rows
+  const IT* hm;
   int len;  // system size (m for columns, n for rows)
 };
 
@@ -67,7 +72,10 @@ struct SylCtl {
 };
 
 // ---------------------------------------------------------------------- residual
-// R = C - A X - X B in double; per-block sum of squares and max |r| into part.
+// R = C - A X - X B in double.  Block (bx, by): columns bx*256 + t, rows
+// [by*kRowsPer, ...); X rows roll through registers, the column neighbours come
+// from the lanes' shared cache lines.  Per-block sum of squares and max |r|
+// into part.
 template <class IT>
 __global__ void __launch_bounds__(kSylBlock) syl_residual_kernel(
     const double* __restrict__ X, const double* __restrict__ C, const double* __restrict__ a_sub,
@@ -76,21 +84,46 @@ __global__ void __launch_bounds__(kSylBlock) syl_residual_kernel(
     double* __restrict__ part, const SylCtl* __restrict__ ctl) {
   __shared__ double sh[kSylBlock / 64][2];
   if (ctl->done) return;
-  const size_t total = (size_t)m * n;
+  const int j = blockIdx.x * kSylBlock + threadIdx.x;
+  const int i0 = blockIdx.y * kRowsPer;
+  const int i1 = i0 + kRowsPer < m ? i0 + kRowsPer : m;
   double s2 = 0.0, mx = 0.0;
-  for (size_t k = (size_t)blockIdx.x * kSylBlock + threadIdx.x; k < total; k += (size_t)gridDim.x * kSylBlock) {
-    const int i = (int)(k / n), j = (int)(k % n);
-    const double x = X[k];
-    double ax = a_diag[i] * x;
-    if (i > 0) ax += a_sub[i - 1] * X[k - n];
-    if (i < m - 1) ax += a_sup[i] * X[k + n];
-    double xb = x * b_diag[j];
-    if (j > 0) xb += X[k - 1] * b_sup[j - 1];
-    if (j < n - 1) xb += X[k + 1] * b_sub[j];
-    const double r = C[k] - ax - xb;
-    R[k] = (IT)r;
-    s2 += r * r;
-    mx = fmax(mx, fabs(r));
+  if (j < n) {
+    // Every load of the block's rows is issued before the arithmetic.
+    // Out-of-range neighbours are read at a clamped in-range index and meet a
+    // zero coefficient: sub/sup of A and B end with a zero entry.
+    const double bd = b_diag[j];
+    const double bl = j > 0 ? b_sup[j > 0 ? j - 1 : 0] : 0.0;  // B[j-1][j]
+    const double br = b_sub[j];                                // B[j+1][j] (0 in the last column)
+    const int dl = j > 0 ? 1 : 0, dr = j + 1 < n ? 1 : 0;
+    double xv[kRowsPer + 2], cv[kRowsPer], xl[kRowsPer], xr[kRowsPer];
+#pragma unroll
+    for (int r = 0; r < kRowsPer + 2; ++r) {
+      int i = i0 - 1 + r;
+      i = i < 0 ? 0 : (i < m ? i : m - 1);
+      xv[r] = X[(size_t)i * n + j];
+    }
+#pragma unroll
+    for (int r = 0; r < kRowsPer; ++r) {
+      const size_t k = (size_t)(i0 + r < m ? i0 + r : m - 1) * n + j;
+      cv[r] = C[k];
+      xl[r] = X[k - dl];
+      xr[r] = X[k + dr];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < kRowsPer; ++r) {
+      const int i = i0 + r;
+      if (i < i1) {
+        const double al = i > 0 ? a_sub[i > 0 ? i - 1 : 0] : 0.0;
+        const double ax = a_diag[i] * xv[r + 1] + al * xv[r] + a_sup[i] * xv[r + 2];
+        const double xb = xv[r + 1] * bd + xl[r] * bl + xr[r] * br;
+        const double res = cv[r] - ax - xb;
+        R[(size_t)i * n + j] = (IT)res;
+        s2 += res * res;
+        mx = fmax(mx, fabs(res));
+      }
+    }
   }
   s2 = wave_sum(s2);
   mx = wave_max(mx);
@@ -105,20 +138,38 @@ __global__ void __launch_bounds__(kSylBlock) syl_residual_kernel(
       a += sh[w][0];
       b = fmax(b, sh[w][1]);
     }
-    part[2 * blockIdx.x] = a;
-    part[2 * blockIdx.x + 1] = b;
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+    part[2 * blk] = a;
+    part[2 * blk + 1] = b;
   }
 }
 
 // Fixed-order combination of the residual partials and the stopping test of
 // Algorithm 1; clears the max |G| word for the sweep that follows.
-__global__ void syl_reduce_kernel(const double* __restrict__ part, int nparts, SylCtl* __restrict__ ctl,
-                                  double* __restrict__ hist, int hist_cap, int scale_rhs, unsigned* __restrict__ gmax) {
-  if (threadIdx.x != 0 || ctl->done) return;
+__global__ void __launch_bounds__(kSylBlock) syl_reduce_kernel(const double* __restrict__ part, int nparts,
+                                                               SylCtl* __restrict__ ctl, double* __restrict__ hist,
+                                                               int hist_cap, int scale_rhs,
+                                                               unsigned* __restrict__ gmax) {
+  __shared__ double sh[kSylBlock / 64][2];
+  if (ctl->done) return;
   double a = 0.0, b = 0.0;
-  for (int k = 0; k < nparts; ++k) {
+  for (int k = threadIdx.x; k < nparts; k += kSylBlock) {
     a += part[2 * k];
     b = fmax(b, part[2 * k + 1]);
+  }
+  a = wave_sum(a);
+  b = wave_max(b);
+  if ((threadIdx.x & 63) == 0) {
+    sh[threadIdx.x >> 6][0] = a;
+    sh[threadIdx.x >> 6][1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  a = 0.0;
+  b = 0.0;
+  for (int w = 0; w < kSylBlock / 64; ++w) {
+    a += sh[w][0];
+    b = fmax(b, sh[w][1]);
   }
   const double rho = sqrt(a);
   const int k = ctl->sweeps;
@@ -146,69 +197,98 @@ __global__ void syl_reduce_kernel(const double* __restrict__ part, int nparts, S
   *gmax = 0u;
 }
 
+// Lane k's value of v for the whole wavefront (k wave-uniform).
+template <class T>
+__device__ __forceinline__ T lane_value(T v, int k) {
+  if constexpr (sizeof(T) == 8) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, k);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), k);
+    return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), k));
+  }
+}
+
 // ---------------------------------------------------------------------- column solves
 // One thread per (column j, chunk c): local recurrences over the chunk's rows.
-// v_i = stor(R_ij * scale) (MODE 1: half storage of the right-hand side).
+// v_i = stor(R_ij * scale) (MODE 1: half storage of the right-hand side).  The
+// chunk's rows are loaded at once (clamped indexes, no branches between the
+// loads); lane k of each wavefront holds the coefficients of row s + k, which
+// the recurrences read with lane broadcasts.  All lanes stay active until the
+// broadcasts are done.
 template <class IT, int MODE>
 __global__ void __launch_bounds__(kSylBlock) syl_col_local_kernel(const IT* __restrict__ R, Factors<IT> F,
                                                                   const SylCtl* __restrict__ ctl, int n,
                                                                   IT* __restrict__ Zh, IT* __restrict__ yend,
-                                                                  IT* __restrict__ zbeg) {
+                                                                  IT* __restrict__ zbeg, IT* __restrict__ zmx) {
   if (ctl->done) return;
   const IT scale = (IT)ctl->scale1;
+  const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * kSylBlock + threadIdx.x;
   const int c = blockIdx.y;
-  const int s = c * kChunk, e = (s + kChunk < F.len) ? s + kChunk : F.len;
-  if (j >= n) return;
+  const int s = c * kChunk;
+  const int len = F.len - s < kChunk ? F.len - s : kChunk;
+  const int ic = s + (lane < len ? lane : len - 1);
+  const IT lk = F.l[ic], sk = F.sup[ic], pk = F.ip[ic];
+  const int jc = j < n ? j : n - 1;
   IT y[kChunk];
+#pragma unroll
+  for (int k = 0; k < kChunk; ++k) y[k] = R[(size_t)(s + (k < len ? k : len - 1)) * n + jc];
+  __builtin_amdgcn_sched_barrier(0);  // every load of the chunk in flight before the recurrences
   IT prev = 0;
 #pragma unroll
   for (int k = 0; k < kChunk; ++k) {
-    const int i = s + k;
-    if (i < e) {
-      const IT v = stor<MODE>(R[(size_t)i * n + j] * scale);
-      prev = v - (k == 0 ? IT(0) : F.l[i] * prev);
-      y[k] = prev;
-    }
+    const IT v = stor<MODE>(y[k] * scale);
+    const IT np = k == 0 ? v : v - lane_value(lk, k) * prev;
+    prev = k < len ? np : prev;
+    y[k] = prev;
   }
-  IT z = 0;
+  IT z = 0, zm = 0;
 #pragma unroll
   for (int k = kChunk - 1; k >= 0; --k) {
-    const int i = s + k;
-    if (i < e) {
-      z = (y[k] - F.sup[i] * z) * F.ip[i];
-      Zh[(size_t)i * n + j] = z;
-    }
+    const IT nz = (y[k] - lane_value(sk, k) * z) * lane_value(pk, k);
+    z = k < len ? nz : z;
+    if (k < len && j < n) Zh[(size_t)(s + k) * n + j] = z;
+    zm = fmax(zm, fabs(z));
   }
-  yend[(size_t)c * n + j] = prev;  // y^ of the chunk's last row
-  zbeg[(size_t)c * n + j] = z;
+  if (j < n) {
+    yend[(size_t)c * n + j] = prev;  // y^ of the chunk's last row
+    zbeg[(size_t)c * n + j] = z;
+    zmx[(size_t)c * n + j] = zm;
+  }
 }
 
 // One thread per column: the chunk-boundary chains.  B_c = y_{s_c - 1}
 // (B_0 = 0), E_c = z_{e_c} (E_last = 0).  The chain inputs are loaded kBatch
-// chunks at a time, so the loads of a batch are in flight together.
-constexpr int kBatch = 16;
+// chunks at a time, so the loads of a batch are in flight together.  With zmx
+// given (column direction), the kernel also bounds max |G| = |gscale| max |z|
+// by max over chunks of max|z^| + |B_c| max|q| + |E_c| max|h| into gmax.
+constexpr int kBatch = 32;
+constexpr int kChainBlock = 64;
 
 template <class IT>
-__global__ void __launch_bounds__(kSylBlock) syl_chain_kernel(const IT* __restrict__ yend, const IT* __restrict__ zbeg,
+__global__ void __launch_bounds__(kChainBlock) syl_chain_kernel(const IT* __restrict__ yend, const IT* __restrict__ zbeg,
                                                               Factors<IT> F, int nchunks, int width,
                                                               IT* __restrict__ Bc, IT* __restrict__ Ec,
+                                                              const IT* __restrict__ zmx, IT gscale,
+                                                              unsigned* __restrict__ gmax,
                                                               const SylCtl* __restrict__ ctl) {
   if (ctl->done) return;
-  const int j = blockIdx.x * kSylBlock + threadIdx.x;
-  if (j >= width) return;
+  const int j = blockIdx.x * kChainBlock + threadIdx.x;
+  IT bound = 0;
+  if (j < width) {
   IT b = 0;
   for (int c0 = 0; c0 < nchunks; c0 += kBatch) {
     IT ye[kBatch], ff[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
-      const int c = c0 + u;
-      if (c < nchunks) {
-        const int e = (c + 1) * kChunk < F.len ? (c + 1) * kChunk : F.len;
-        ye[u] = yend[(size_t)c * width + j];
-        ff[u] = F.f[e - 1];
-      }
+      const int c = c0 + u < nchunks ? c0 + u : nchunks - 1;
+      const int e = (c + 1) * kChunk < F.len ? (c + 1) * kChunk : F.len;
+      ye[u] = yend[(size_t)c * width + j];
+      ff[u] = F.f[e - 1];
     }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
       const int c = c0 + u;
@@ -220,55 +300,33 @@ __global__ void __launch_bounds__(kSylBlock) syl_chain_kernel(const IT* __restri
   }
   IT ez = 0;
   for (int c1 = nchunks - 1; c1 >= 0; c1 -= kBatch) {
-    IT zb[kBatch], bb[kBatch], qq[kBatch], hh[kBatch];
+    IT zb[kBatch], bb[kBatch], qq[kBatch], hh[kBatch], zm[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
-      const int c = c1 - u;
-      if (c >= 0) {
-        const int s = c * kChunk;
-        zb[u] = zbeg[(size_t)c * width + j];
-        bb[u] = Bc[(size_t)c * width + j];
-        qq[u] = F.q[s];
-        hh[u] = F.h[s];
-      }
+      const int c = c1 - u >= 0 ? c1 - u : 0;
+      const int s = c * kChunk;
+      zb[u] = zbeg[(size_t)c * width + j];
+      bb[u] = Bc[(size_t)c * width + j];
+      qq[u] = F.q[s];
+      hh[u] = F.h[s];
+      zm[u] = zmx ? zmx[(size_t)c * width + j] : IT(0);
     }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
       const int c = c1 - u;
       if (c >= 0) {
         Ec[(size_t)c * width + j] = ez;
+        if (zmx) bound = fmax(bound, zm[u] + fabs(bb[u]) * F.qm[c] + fabs(ez) * F.hm[c]);
         ez = zb[u] + bb[u] * qq[u] + ez * hh[u];
       }
     }
   }
-}
-
-// z = z^ + B q + E h per element; G = (2 - omega) alpha z (in place of Zh),
-// block max of |G| into gmax (bits of a non-negative float: monotone).
-template <class IT>
-__global__ void __launch_bounds__(kSylBlock) syl_col_fix_kernel(IT* __restrict__ Zh, const IT* __restrict__ Bc,
-                                                                const IT* __restrict__ Ec, Factors<IT> F, IT gscale,
-                                                                int m, int n, unsigned* __restrict__ gmax,
-                                                                const SylCtl* __restrict__ ctl) {
-  __shared__ float sh[kSylBlock / 64];
-  if (ctl->done) return;
-  const size_t total = (size_t)m * n;
-  float mx = 0.f;
-  for (size_t k = (size_t)blockIdx.x * kSylBlock + threadIdx.x; k < total; k += (size_t)gridDim.x * kSylBlock) {
-    const int i = (int)(k / n), j = (int)(k % n);
-    const int c = i / kChunk;
-    const IT z = Zh[k] + Bc[(size_t)c * n + j] * F.q[i] + Ec[(size_t)c * n + j] * F.h[i];
-    const IT g = gscale * z;
-    Zh[k] = g;
-    mx = fmaxf(mx, fabsf((float)g));
   }
-  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float b = 0.f;
-    for (int w = 0; w < kSylBlock / 64; ++w) b = fmaxf(b, sh[w]);
-    atomicMax(gmax, __float_as_uint(b));
+  if (zmx) {
+    float v = (float)(fabs(gscale) * bound);
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(gmax, __float_as_uint(v));
   }
 }
 
@@ -283,60 +341,93 @@ __device__ __forceinline__ float g_scale(const unsigned* gmax) {
 }
 
 // ---------------------------------------------------------------------- row solves
-// One wavefront per tile of 64 rows x kChunk columns: the tile passes through
-// LDS so that global loads and stores run along the rows; lane t then runs the
-// chunk-local recurrences of row r0 + t.  v_ij = stor(G_ij * 2^-e2).
+// One wavefront per tile of 64 rows (one column chunk) x kChunk columns; lane t
+// runs the chunk-local recurrences of row r0 + t.  The tile passes through LDS
+// in slabs of kSlab columns so that global loads and stores run along the
+// rows.  Reading a slab finishes the column solves, z = z^ + B q + E h, and
+// forms v_ij = stor(G_ij 2^-e2) with G = (2 - omega) alpha z.  Lane t holds
+// the row solve's coefficients and the column chains of column s + t, and the
+// column coefficients q, h of row r0 + t.
+constexpr int kSlab = 16;
+
 template <class IT, int MODE>
-__global__ void __launch_bounds__(64) syl_row_local_kernel(const IT* __restrict__ G, Factors<IT> F,
-                                                           const unsigned* __restrict__ gmax, int m, int n,
-                                                           IT* __restrict__ Zh, IT* __restrict__ yend,
+__global__ void __launch_bounds__(64) syl_row_local_kernel(const IT* __restrict__ Zc, const IT* __restrict__ Bcol,
+                                                           const IT* __restrict__ Ecol, Factors<IT> Fc, IT gscale,
+                                                           Factors<IT> F, const unsigned* __restrict__ gmax, int m,
+                                                           int n, IT* __restrict__ Zh, IT* __restrict__ yend,
                                                            IT* __restrict__ zbeg, const SylCtl* __restrict__ ctl) {
-  __shared__ IT tile[64][kChunk + 1];
+  __shared__ IT tile[64][kSlab + 1];
   if (ctl->done) return;
   const int t = threadIdx.x;
   const int c = blockIdx.x;
   const int r0 = blockIdx.y * 64;
-  const int s = c * kChunk, e = (s + kChunk < n) ? s + kChunk : n;
-  const IT sc = (IT)g_scale(gmax);
-  for (int k = 0; k < 64; ++k) {
-    const int i = r0 + k, j = s + t;
-    tile[k][t] = (i < m && j < e) ? stor<MODE>(G[(size_t)i * n + j] * sc) : IT(0);
-  }
-  __syncthreads();
+  const int s = c * kChunk;
+  const int len = n - s < kChunk ? n - s : kChunk;
+  const IT sc = (IT)g_scale(gmax) * gscale;
+  const int jt = s + (t < len ? t : len - 1);
+  const IT lk = F.l[jt], sk = F.sup[jt], pk = F.ip[jt];
+  const IT bq = Bcol[(size_t)blockIdx.y * n + jt], eh = Ecol[(size_t)blockIdx.y * n + jt];
   const int row = r0 + t;
+  const int rc = row < m ? row : m - 1;
+  const IT qr = Fc.q[rc], hr = Fc.h[rc];
+  const int sl = t % kSlab, sr = t / kSlab;  // slab column and first row of this lane's slab loads
+  constexpr int kPer = 64 * kSlab / 64;      // slab elements per lane
   IT y[kChunk];
   IT prev = 0;
 #pragma unroll
-  for (int k = 0; k < kChunk; ++k) {
-    const int j = s + k;
-    if (j < e) {
-      const IT v = tile[t][k];
-      prev = v - (k == 0 ? IT(0) : F.l[j] * prev);
-      y[k] = prev;
+  for (int q = 0; q < kChunk / kSlab; ++q) {
+    const int col = q * kSlab + sl;
+    const int jj = s + (col < len ? col : len - 1);
+    IT v[kPer];
+#pragma unroll
+    for (int kk = 0; kk < kPer; ++kk) {
+      const int i = r0 + sr + (64 / kSlab) * kk;
+      v[kk] = Zc[(size_t)(i < m ? i : m - 1) * n + jj];
     }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kk = 0; kk < kPer; ++kk) tile[sr + (64 / kSlab) * kk][sl] = v[kk];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSlab; ++k) {
+      const int kc = q * kSlab + k;
+      const IT zc = tile[t][k] + lane_value(bq, kc) * qr + lane_value(eh, kc) * hr;
+      const IT vv = stor<MODE>(zc * sc);
+      const IT np = kc == 0 ? vv : vv - lane_value(lk, kc) * prev;
+      prev = kc < len ? np : prev;
+      y[kc] = prev;
+    }
+    __syncthreads();
   }
   IT z = 0;
 #pragma unroll
-  for (int k = kChunk - 1; k >= 0; --k) {
-    const int j = s + k;
-    if (j < e) {
-      z = (y[k] - F.sup[j] * z) * F.ip[j];
+  for (int q = kChunk / kSlab - 1; q >= 0; --q) {
+#pragma unroll
+    for (int k = kSlab - 1; k >= 0; --k) {
+      const int kc = q * kSlab + k;
+      const IT nz = (y[kc] - lane_value(sk, kc) * z) * lane_value(pk, kc);
+      z = kc < len ? nz : z;
       tile[t][k] = z;
     }
+    __syncthreads();
+    const int col = q * kSlab + sl;
+#pragma unroll
+    for (int kk = 0; kk < kPer; ++kk) {
+      const int i = r0 + sr + (64 / kSlab) * kk;
+      if (i < m && col < len) Zh[(size_t)i * n + s + col] = tile[sr + (64 / kSlab) * kk][sl];
+    }
+    __syncthreads();
   }
   if (row < m) {
     yend[(size_t)c * m + row] = prev;
     zbeg[(size_t)c * m + row] = z;
   }
-  __syncthreads();
-  for (int k = 0; k < 64; ++k) {
-    const int i = r0 + k, j = s + t;
-    if (i < m && j < e) Zh[(size_t)i * n + j] = tile[k][t];
-  }
 }
 
 // y = z^ + B q + E h along the rows, stored in the inner precision, then
-// X += y 2^(e1 + e2) in double.
+// X += y 2^(e1 + e2) in double.  Block (bx, by): columns bx*256 + t, rows
+// [by*kRowsPer, ...); a wavefront's 64 columns lie in one chunk, so B and E
+// are wave-uniform loads.
 template <class IT, int MODE>
 __global__ void __launch_bounds__(kSylBlock) syl_row_fix_update_kernel(const IT* __restrict__ Zh,
                                                                        const IT* __restrict__ Bc,
@@ -345,13 +436,31 @@ __global__ void __launch_bounds__(kSylBlock) syl_row_fix_update_kernel(const IT*
                                                                        const SylCtl* __restrict__ ctl, int m, int n,
                                                                        double* __restrict__ X) {
   if (ctl->done) return;
-  const size_t total = (size_t)m * n;
+  const int j = blockIdx.x * kSylBlock + threadIdx.x;
+  if (j >= n) return;
   const double unscale = 1.0 / (ctl->scale1 * (double)g_scale(gmax));
-  for (size_t k = (size_t)blockIdx.x * kSylBlock + threadIdx.x; k < total; k += (size_t)gridDim.x * kSylBlock) {
-    const int i = (int)(k / n), j = (int)(k % n);
-    const int c = j / kChunk;
-    const IT y = stor<MODE>(Zh[k] + Bc[(size_t)c * m + i] * F.q[j] + Ec[(size_t)c * m + i] * F.h[j]);
-    X[k] += (double)y * unscale;
+  const int c = j / kChunk;
+  const IT q = F.q[j], h = F.h[j];
+  const int i0 = blockIdx.y * kRowsPer;
+  IT zv[kRowsPer], bv[kRowsPer], ev[kRowsPer];
+  double xo[kRowsPer];
+#pragma unroll
+  for (int r = 0; r < kRowsPer; ++r) {
+    const int i = i0 + r < m ? i0 + r : m - 1;
+    const size_t k = (size_t)i * n + j;
+    zv[r] = Zh[k];
+    bv[r] = Bc[(size_t)c * m + i];
+    ev[r] = Ec[(size_t)c * m + i];
+    xo[r] = X[k];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int r = 0; r < kRowsPer; ++r) {
+    const int i = i0 + r;
+    if (i < m) {
+      const IT y = stor<MODE>(zv[r] + bv[r] * q + ev[r] * h);
+      X[(size_t)i * n + j] = xo[r] + (double)y * unscale;
+    }
   }
 }
 
@@ -368,8 +477,8 @@ struct SylSystem {
   double* dC = nullptr;
   void* R = nullptr;     // m*n inner type
   void* Zh = nullptr;    // m*n inner type
-  void* chain = nullptr; // yend, zbeg, B, E: 4 * chunks * max(m, n)
-  void* coef = nullptr;  // 6 * (m + n) inner type
+  void* chain = nullptr; // yend, zbeg, B, E, max|z^|: 5 * chunks * max(m, n)
+  void* coef = nullptr;  // per direction l, 1/p, sup, f, q, h and per-chunk max|q|, max|h|
   double* part = nullptr;
   SylCtl* ctl = nullptr;       // device
   SylCtl* ctl_host = nullptr;  // pinned host copy
@@ -404,7 +513,8 @@ static void factor(const std::vector<double>& sub0, const std::vector<double>& d
       sup[i] = rd(sup0[i]);
     }
   }
-  out.assign(6 * (size_t)len, 0.0);
+  const int nch = (len + kChunk - 1) / kChunk;
+  out.assign(6 * (size_t)len + 2 * (size_t)nch, 0.0);
   double* l = out.data();
   double* ip = l + len;
   double* su = ip + len;
@@ -428,12 +538,20 @@ static void factor(const std::vector<double>& sub0, const std::vector<double>& d
       q[i] = (f[i] - (i + 1 < e ? su[i] * q[i + 1] : 0.0)) * ip[i];
       h[i] = -su[i] * ip[i] * (i + 1 < e ? h[i + 1] : 1.0);
     }
+    double qm = 0.0, hm = 0.0;
+    for (int i = s; i < e; ++i) {
+      qm = std::fmax(qm, std::fabs(q[i]));
+      hm = std::fmax(hm, std::fabs(h[i]));
+    }
+    // rounded up by a few ulps so that the bound survives the conversion to the inner type
+    out[6 * (size_t)len + s / kChunk] = qm * (1.0 + 1e-6);
+    out[6 * (size_t)len + nch + s / kChunk] = hm * (1.0 + 1e-6);
   }
 }
 
 template <class IT>
 static gadi_status upload_coef(SylSystem& S, const std::vector<double>& col, const std::vector<double>& row) {
-  std::vector<IT> buf(6 * (size_t)(S.m + S.n));
+  std::vector<IT> buf(col.size() + row.size());
   for (size_t k = 0; k < col.size(); ++k) buf[k] = (IT)col[k];
   for (size_t k = 0; k < row.size(); ++k) buf[col.size() + k] = (IT)row[k];
   GADI_HIP_CHECK(hipMemcpyAsync(S.coef, buf.data(), buf.size() * sizeof(IT), hipMemcpyHostToDevice, S.stream));
@@ -441,11 +559,16 @@ static gadi_status upload_coef(SylSystem& S, const std::vector<double>& col, con
   return GADI_OK;
 }
 
+static size_t coef_len(int len) { return 6 * (size_t)len + 2 * (size_t)((len + kChunk - 1) / kChunk); }
+
 template <class IT>
 static Factors<IT> factors_at(const SylSystem& S, int which) {
-  const IT* base = (const IT*)S.coef + (which == 0 ? 0 : 6 * (size_t)S.m);
+  const IT* base = (const IT*)S.coef + (which == 0 ? 0 : coef_len(S.m));
   const int len = which == 0 ? S.m : S.n;
-  return Factors<IT>{base, base + len, base + 2 * len, base + 3 * len, base + 4 * len, base + 5 * len, len};
+  const int nch = (len + kChunk - 1) / kChunk;
+  const IT* qm = base + 6 * (size_t)len;
+  return Factors<IT>{base,           base + len,     base + 2 * len, base + 3 * len, base + 4 * len,
+                     base + 5 * len, qm,             qm + nch,       len};
 }
 
 static int grid_of(size_t total) {
@@ -465,26 +588,28 @@ static void enqueue_sweep(SylSystem& S, double alpha, double omega) {
   IT* zbeg = yend + pw;
   IT* Bc = zbeg + pw;
   IT* Ec = Bc + pw;
+  IT* zmx = Ec + pw;
   const Factors<IT> Fc = factors_at<IT>(S, 0), Fr = factors_at<IT>(S, 1);
+  const IT gs = (IT)((2.0 - omega) * alpha);
   IT* R = (IT*)S.R;
   IT* Zh = (IT*)S.Zh;
-  hipLaunchKernelGGL((syl_residual_kernel<IT>), dim3(S.nparts), dim3(kSylBlock), 0, S.stream, S.dX, S.dC, S.dA,
-                     S.dA + m, S.dA + 2 * m, S.dB, S.dB + n, S.dB + 2 * n, R, m, n, S.part, S.ctl);
-  hipLaunchKernelGGL(syl_reduce_kernel, dim3(1), dim3(64), 0, S.stream, S.part, S.nparts, S.ctl, S.dhist, S.hist_cap,
-                     MODE == 2 ? 0 : 1, S.gmax);
+  const dim3 g2((n + kSylBlock - 1) / kSylBlock, (m + kRowsPer - 1) / kRowsPer);
+  hipLaunchKernelGGL((syl_residual_kernel<IT>), g2, dim3(kSylBlock), 0, S.stream, S.dX, S.dC, S.dA, S.dA + m,
+                     S.dA + 2 * m, S.dB, S.dB + n, S.dB + 2 * n, R, m, n, S.part, S.ctl);
+  hipLaunchKernelGGL(syl_reduce_kernel, dim3(1), dim3(kSylBlock), 0, S.stream, S.part, S.nparts, S.ctl, S.dhist,
+                     S.hist_cap, MODE == 2 ? 0 : 1, S.gmax);
   hipLaunchKernelGGL((syl_col_local_kernel<IT, MODE>), dim3((n + kSylBlock - 1) / kSylBlock, pc), dim3(kSylBlock), 0,
-                     S.stream, R, Fc, S.ctl, n, Zh, yend, zbeg);
-  hipLaunchKernelGGL((syl_chain_kernel<IT>), dim3((n + kSylBlock - 1) / kSylBlock), dim3(kSylBlock), 0, S.stream,
-                     yend, zbeg, Fc, pc, n, Bc, Ec, S.ctl);
-  hipLaunchKernelGGL((syl_col_fix_kernel<IT>), dim3(grid_of((size_t)m * n)), dim3(kSylBlock), 0, S.stream, Zh, Bc, Ec,
-                     Fc, (IT)((2.0 - omega) * alpha), m, n, S.gmax, S.ctl);
-  // G is in Zh; the row solves write their chunk-local solutions to R
-  hipLaunchKernelGGL((syl_row_local_kernel<IT, MODE>), dim3(pr, (m + 63) / 64), dim3(64), 0, S.stream, Zh, Fr, S.gmax,
-                     m, n, R, yend, zbeg, S.ctl);
-  hipLaunchKernelGGL((syl_chain_kernel<IT>), dim3((m + kSylBlock - 1) / kSylBlock), dim3(kSylBlock), 0, S.stream,
-                     yend, zbeg, Fr, pr, m, Bc, Ec, S.ctl);
-  hipLaunchKernelGGL((syl_row_fix_update_kernel<IT, MODE>), dim3(grid_of((size_t)m * n)), dim3(kSylBlock), 0,
-                     S.stream, R, Bc, Ec, Fr, S.gmax, S.ctl, m, n, S.dX);
+                     S.stream, R, Fc, S.ctl, n, Zh, yend, zbeg, zmx);
+  hipLaunchKernelGGL((syl_chain_kernel<IT>), dim3((n + kChainBlock - 1) / kChainBlock), dim3(kChainBlock), 0, S.stream,
+                     yend, zbeg, Fc, pc, n, Bc, Ec, zmx, gs, S.gmax, S.ctl);
+  // the row solves read z^ (Zh) and the column chains (Bc, Ec), and write their
+  // chunk-local solutions to R and their chain inputs to yend, zbeg
+  hipLaunchKernelGGL((syl_row_local_kernel<IT, MODE>), dim3(pr, (m + 63) / 64), dim3(64), 0, S.stream, Zh, Bc, Ec, Fc,
+                     gs, Fr, S.gmax, m, n, R, yend, zbeg, S.ctl);
+  hipLaunchKernelGGL((syl_chain_kernel<IT>), dim3((m + kChainBlock - 1) / kChainBlock), dim3(kChainBlock), 0, S.stream,
+                     yend, zbeg, Fr, pr, m, Bc, Ec, (const IT*)nullptr, IT(0), S.gmax, S.ctl);
+  hipLaunchKernelGGL((syl_row_fix_update_kernel<IT, MODE>), g2, dim3(kSylBlock), 0, S.stream, R, Bc, Ec, Fr, S.gmax,
+                     S.ctl, m, n, S.dX);
 }
 
 template <class IT, int MODE>
@@ -581,8 +706,10 @@ extern "C" gadi_status gadi_sylv_setup(int32_t m, int32_t n, const double* a_sub
   if (hipGetDevice(&S.device) != hipSuccess) return fail(GADI_EHIP);
   const size_t mn = (size_t)m * n;
   const size_t w = (size_t)(m > n ? m : n);
+  static_assert(((kSylMax + kSylBlock - 1) / kSylBlock) * ((kSylMax + kRowsPer - 1) / kRowsPer) < (1 << 30),
+                "partials fit int");
   const size_t pmax = (size_t)(chunks_of(m) > chunks_of(n) ? chunks_of(m) : chunks_of(n));
-  S.nparts = grid_of(mn);
+  S.nparts = ((n + kSylBlock - 1) / kSylBlock) * ((m + kRowsPer - 1) / kRowsPer);
   std::vector<double> a3(3 * (size_t)m), b3(3 * (size_t)n);
   for (int i = 0; i < m; ++i) {
     a3[i] = S.a_sub[i];
@@ -597,7 +724,7 @@ extern "C" gadi_status gadi_sylv_setup(int32_t m, int32_t n, const double* a_sub
   if (hipMalloc((void**)&S.dA, a3.size() * 8) != hipSuccess || hipMalloc((void**)&S.dB, b3.size() * 8) != hipSuccess ||
       hipMalloc((void**)&S.dX, mn * 8) != hipSuccess || hipMalloc((void**)&S.dC, mn * 8) != hipSuccess ||
       hipMalloc(&S.R, mn * 8) != hipSuccess || hipMalloc(&S.Zh, mn * 8) != hipSuccess ||
-      hipMalloc(&S.chain, 4 * pmax * w * 8) != hipSuccess || hipMalloc(&S.coef, 6 * (size_t)(m + n) * 8) != hipSuccess ||
+      hipMalloc(&S.chain, 5 * pmax * w * 8) != hipSuccess || hipMalloc(&S.coef, (coef_len(m) + coef_len(n)) * 8) != hipSuccess ||
       hipMalloc((void**)&S.part, 2 * (size_t)S.nparts * 8) != hipSuccess ||
       hipMalloc((void**)&S.ctl, sizeof(SylCtl)) != hipSuccess ||
       hipHostMalloc((void**)&S.ctl_host, sizeof(SylCtl)) != hipSuccess ||
