@@ -51,6 +51,14 @@ class SolveInfo(ctypes.Structure):
 
 def _load():
     path = _build.ensure_built()
+    # One HIP runtime per process: torch ships its own libamdhip64.so.7 and
+    # loads it by path.  Loaded first, it also satisfies libgadi's dependency
+    # of that name; loaded after libgadi, it would be a second runtime beside
+    # the system one, and whichever initialises second finds no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     P = ctypes.POINTER

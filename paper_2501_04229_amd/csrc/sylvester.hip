@@ -703,7 +703,10 @@ extern "C" gadi_status gadi_sylv_setup(int32_t m, int32_t n, const double* a_sub
     gadi_sylv_destroy(h);
     return st;
   };
-  if (hipGetDevice(&S.device) != hipSuccess) return fail(GADI_EHIP);
+  {
+    const hipError_t e = hipGetDevice(&S.device);
+    if (e != hipSuccess) return fail(fail_hip(e, "hipGetDevice", __FILE__, __LINE__));
+  }
   const size_t mn = (size_t)m * n;
   const size_t w = (size_t)(m > n ? m : n);
   static_assert(((kSylMax + kSylBlock - 1) / kSylBlock) * ((kSylMax + kRowsPer - 1) / kRowsPer) < (1 << 30),
@@ -731,9 +734,11 @@ extern "C" gadi_status gadi_sylv_setup(int32_t m, int32_t n, const double* a_sub
       hipMalloc((void**)&S.gmax, 4) != hipSuccess ||
       hipEventCreate(&S.ev0) != hipSuccess || hipEventCreate(&S.ev1) != hipSuccess)
     return fail(GADI_ENOMEM);
-  if (hipMemcpy(S.dA, a3.data(), a3.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(S.dB, b3.data(), b3.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
-    return fail(GADI_EHIP);
+  for (int k = 0; k < 2; ++k) {
+    const hipError_t e = k == 0 ? hipMemcpy(S.dA, a3.data(), a3.size() * 8, hipMemcpyHostToDevice)
+                                : hipMemcpy(S.dB, b3.data(), b3.size() * 8, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(fail_hip(e, "hipMemcpy of the coefficients", __FILE__, __LINE__));
+  }
   *out = h;
   return GADI_OK;
 }

@@ -60,3 +60,16 @@ def test_argument_checks_without_gpu():
     assert L.gadi_ir_solve(None, None, None, 0.5, 0.5, 1e-10, None, None) == gadi.EINVAL
     assert L.gadi_destroy(None) == gadi.EINVAL
     assert L.gadi_spmv(None, 0, 1.0, None, None) == gadi.EINVAL
+
+
+def test_one_hip_runtime_when_the_package_is_imported_first():
+    """Imported before torch (as `python -m paper_2501_04229_amd.<module>` does),
+    the package must still leave one libamdhip64 in the process: a second
+    runtime beside torch's finds no device."""
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_2501_04229_amd, torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n") % ROOT
+    out = subprocess.run([os.sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip().splitlines()[-1] == "1"
