@@ -12,8 +12,8 @@ namespace gadi {
 // pattern policies (uniform diagonal layout: offsets in scalar registers).
 // A block owns U consecutive tiles (an XCD-contiguous remap of the blocks,
 // as in the solver, measured slower here at 256^3).  x has the caller's
-// length n: rows past
-// n read no x (their diagonal term is zero) and write no y.
+// length n: rows past n read x at row n - 1 (an unconditional load, so no
+// branch drains the loads in flight) and write no y.
 constexpr int kSpmvBlock = 256;
 
 // y = A x in double (the residual's operator, step 1 of Algorithm 1)
@@ -30,7 +30,7 @@ __global__ void __launch_bounds__(kSpmvBlock) spmv_a64_kernel(Pat pat, const dou
         struct {
           double d, xr;
           decltype(pat.gather(0u, off, gx)) g;
-        } l{at(diag, row), row < (unsigned)n ? at(x, row) : 0.0, pat.gather(row, off, gx)};
+        } l{at(diag, row), at(x, row < (unsigned)n ? row : (unsigned)n - 1u), pat.gather(row, off, gx)};
         return l;
       },
       [&](const auto& l) { return l.d * l.xr + pat.template dot<double>(l.g, [](double v) { return v; }); },
@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(kSpmvBlock) spmv_h_kernel(Pat pat, const MT* _
         struct {
           MT d, xr;
           decltype(pat.gather(0u, off, gx)) g;
-        } l{at(diag, row), row < (unsigned)n ? at(x, row) : MT(0), pat.gather(row, off, gx)};
+        } l{at(diag, row), at(x, row < (unsigned)n ? row : (unsigned)n - 1u), pat.gather(row, off, gx)};
         return l;
       },
       [&](const auto& l) {
@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(kSpmvBlock) spmv_s16_kernel(Pat pat, const __h
         struct {
           __half xr;
           decltype(pat.gather(0u, off, gx)) g;
-        } l{row < (unsigned)n ? at(x, row) : __half(0.f), pat.gather(row, off, gx)};
+        } l{at(x, row < (unsigned)n ? row : (unsigned)n - 1u), pat.gather(row, off, gx)};
         return l;
       },
       [&](const auto& l) {
@@ -173,8 +173,8 @@ extern "C" gadi_status gadi_spmv(gadi_handle* h, int32_t which, double alpha, co
   System& s = h->sys;
   GADI_HIP_CHECK(hipSetDevice(s.device));
   switch (s.dia_uniform) {
-    case 4: launch_products<4, 2>(s, uniform_pattern<4>(s), which, alpha, x, y); break;
-    case 6: launch_products<4, 2>(s, uniform_pattern<6>(s), which, alpha, x, y); break;
+    case 4: launch_products<2, 2>(s, uniform_pattern<4>(s), which, alpha, x, y); break;
+    case 6: launch_products<2, 2>(s, uniform_pattern<6>(s), which, alpha, x, y); break;
     default:
       launch_products<1, 1>(s, PatGeneric{Pattern{s.slice_ptr, s.col, s.slice_dia, s.dia_off, s.n - 1}}, which, alpha,
                          x, y);
