@@ -271,6 +271,34 @@ int32_t gadi_sylv_get_history(gadi_sylv* h, double* out, int32_t cap);
 gadi_status gadi_sylv_set_stream(gadi_sylv* h, void* hip_stream);
 gadi_status gadi_sylv_destroy(gadi_sylv* h);
 
+/* ---- Gaussian-process regression of alpha on the problem size (Section 3.3) ----
+ * The paper's predictor maps the size n of small systems of one structure to
+ * their best alpha and extrapolates to large n.  Model (host code, double):
+ *   y(x) = b0 + b1 x + f(x) + e,  f ~ GP(0, sf2 exp(-(x - x')^2 / (2 l^2))),
+ *   e ~ N(0, sn2),
+ * the linear mean by least squares, the GP on its residuals (none when every
+ * residual is at most 1e-12 max(1, max |y|)).  l, sn2 / sf2
+ * maximise the log marginal likelihood over a fixed grid (l: 25 log-spaced
+ * values in [0.1 s, 10 s], s the spread of x; sn2 / sf2: 13 log-spaced values
+ * in [1e-6, 1]); sf2 is profiled out.  The callers take x = log2 n,
+ * y = log10 alpha. */
+typedef struct gadi_gpr gadi_gpr;
+
+/* Fit to m points (host arrays x[m], y[m], finite; 1 <= m <= 4096).  On
+ * success *out owns the model.  EINVAL for bad arguments or when no grid point
+ * gives a positive definite kernel matrix. */
+gadi_status gadi_gpr_fit(const double* x, const double* y, int32_t m, gadi_gpr** out);
+
+/* Latent posterior mean (and standard deviation if sd is not NULL) at q host
+ * points xq[q]; mean and sd are host arrays of q entries. */
+gadi_status gadi_gpr_predict(const gadi_gpr* g, const double* xq, int32_t q, double* mean, double* sd);
+
+/* out[6] = b0, b1, l, sf2, sn2, log marginal likelihood of the residuals
+ * (+inf when the data are exactly linear and the GP part is zero). */
+gadi_status gadi_gpr_params(const gadi_gpr* g, double* out);
+
+gadi_status gadi_gpr_destroy(gadi_gpr* g);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,7 +11,8 @@ definitions (Rasmussen and Williams, Gaussian Processes for Machine Learning,
     k(x, x') = sf2 exp(-(x - x')^2 / (2 ell^2)),
 
 with the linear mean fitted by least squares and the GP fitted to its
-residuals.  Hyperparameters maximise the log marginal likelihood of the
+residuals (no GP when every residual is at most 1e-12 max(1, max |y|): the
+data are a line up to rounding).  Hyperparameters maximise the log marginal likelihood of the
 residuals over ell in 25 log-spaced values in [0.1 s, 10 s] (s = spread of x,
 1 if zero) and eta = sn2 / sf2 in 13 log-spaced values in [1e-6, 1], with sf2
 at its maximiser for each (ell, eta); the first grid point wins ties.
@@ -76,7 +77,7 @@ def fit(x, y):
     e = y - b0 - b1 * x
     s = float(np.ptp(x)) or 1.0
     out = {"b0": b0, "b1": b1, "x": x, "e": e}
-    if not np.any(e != 0.0):
+    if np.max(np.abs(e)) <= 1e-12 * max(1.0, float(np.max(np.abs(y)))):
         out.update(ell=s, sf2=0.0, sn2=0.0, lml=np.inf)
         return out
     best = None

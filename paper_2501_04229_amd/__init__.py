@@ -95,6 +95,10 @@ def _load():
         "gadi_sylv_get_history": (i32, [vp, P(f64), i32]),
         "gadi_sylv_set_stream": (i32, [vp, vp]),
         "gadi_sylv_destroy": (i32, [vp]),
+        "gadi_gpr_fit": (i32, [P(f64), P(f64), i32, P(vp)]),
+        "gadi_gpr_predict": (i32, [vp, P(f64), i32, P(f64), P(f64)]),
+        "gadi_gpr_params": (i32, [vp, P(f64)]),
+        "gadi_gpr_destroy": (i32, [vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)

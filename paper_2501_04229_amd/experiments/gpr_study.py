@@ -1,0 +1,163 @@
+"""The paper's GPR parameter prediction (Section 3.3, Table "pred32").
+
+    python -m paper_2501_04229_amd.experiments.gpr_study [--out FILE]
+
+1. Training sets: for small 3-D convection-diffusion systems of the bench's
+   structure (beta = 20, x* ~ U(-1, 1)), the best alpha at omega = 0.5 is
+   found by a coarse log scan of alpha in [0.03, 30] followed by a
+   dichotomous search (evaluate at mid -+ delta, keep the better half) on
+   log10 alpha; the objective is the work of a solve to RES 1e-6 (phases:
+   inner CG steps + 2 CGNE steps + 5 per sweep).  Once with single-precision
+   solves (u_r = u = u_f = single, the paper's FP32 training set) and once
+   with double solves (FP64).
+2. GPR of log10 alpha on log2 n (libgadi's gadi_gpr_*), extrapolated to
+   n = 32, 64, 128 with the paper's retraining: each prediction joins the
+   training set before the next size.  Table pred32 compares the alphas
+   predicted from the two training sets.
+3. FP16-IR solves to RES 1e-10 at n = 32, 64, 128 with the GPR alpha
+   (omega = 0.5), the MLP's (alpha, omega) and the default (0.5, 0.5): sweeps
+   and device seconds.
+
+The paper prints neither the training sizes, omega, the tolerances nor the
+search's details; they are parameters here.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import gadi_inputs as gi  # noqa: E402
+import paper_2501_04229_amd as gadi  # noqa: E402
+from paper_2501_04229_amd import predictor as pr  # noqa: E402
+from paper_2501_04229_amd.predictor import gpr  # noqa: E402
+
+BETA = 20.0
+OMEGA = 0.5
+
+
+def system(n, device):
+    import torch
+    A = gi.convdiff(n, 3, BETA)
+    _, b = gi.rhs_for(A, "uniform", 0)
+    return A, gadi.System(A), torch.from_numpy(b).to(device)
+
+
+def best_alpha(g, b, prec, tol, maxit, maxit_inner, coarse=7, delta=0.01, width=0.08):
+    """Coarse scan of log10 alpha in [-1.5, 1.5], then a dichotomous search
+    around the best scan point.  A solve that fails or exceeds the sweep or
+    inner-step caps counts as infinite work.  Returns (alpha, work,
+    evaluations)."""
+    cache = {}
+
+    def f(u):
+        key = round(u, 6)
+        if key not in cache:
+            _, info = g.solve(b, 10.0 ** u, OMEGA, tol=tol, prec=prec, maxit_outer=maxit,
+                              maxit_inner=maxit_inner)
+            cache[key] = pr.work(info) if info["status"] == gadi.OK else math.inf
+        return cache[key]
+
+    grid = np.linspace(-1.5, 1.5, coarse)
+    vals = [f(u) for u in grid]
+    k = int(np.argmin(vals))
+    lo, hi = grid[max(k - 1, 0)], grid[min(k + 1, coarse - 1)]
+    if not math.isfinite(vals[k]):
+        return math.nan, math.inf, len(cache)
+    while hi - lo > width:
+        mid = 0.5 * (lo + hi)
+        a, c = f(mid - delta), f(mid + delta)
+        if a < c:
+            hi = mid + delta
+        elif c < a:
+            lo = mid - delta
+        else:
+            lo, hi = mid - delta, mid + delta
+    cand = {u: v for u, v in cache.items() if lo - 1e-9 <= u <= hi + 1e-9} or cache
+    u_best = min(cand, key=lambda u: (cand[u], -u))
+    return 10.0 ** u_best, cache[u_best], len(cache)
+
+
+def training(sizes, device, tol, maxit, maxit_inner):
+    rows = []
+    for n in sizes:
+        A, g, b = system(n, device)
+        for prec, name in (("s-s-s", "fp32"), ("fp64", "fp64")):
+            t0 = time.time()
+            a, w, ev = best_alpha(g, b, prec, tol, maxit, maxit_inner)
+            rows.append({"n": n, "prec": name, "alpha": a, "work": w, "evaluations": ev,
+                         "wall_seconds": time.time() - t0})
+            print(f"[train] n={n} {name}: alpha* {a:.4g} (work {w:.0f}, {ev} solves, {time.time() - t0:.1f} s)",
+                  flush=True)
+        g.close()
+    return rows
+
+
+def apply(targets, alphas, device, mlp):
+    rows = []
+    for n in targets:
+        A, g, b = system(n, device)
+        runs = [("default", 0.5, 0.5)]
+        for name, al in alphas[n].items():
+            runs.append((f"gpr_{name}", al, OMEGA))
+        if mlp is not None:
+            a, w = pr.predict(mlp, g, A)
+            runs.append(("mlp", float(a), float(w)))
+        for name, a, w in runs:
+            g.solve(b, a, w, tol=1e-10, prec="fp16", maxit_outer=3)  # tuner and warm-up
+            _, info = g.solve(b, a, w, tol=1e-10, prec="fp16", maxit_outer=20000)
+            rows.append({"n": n, "run": name, "alpha": a, "omega": w, "status": info["status_str"],
+                         "sweeps": info["outer_sweeps"], "seconds": info["seconds"], "relres": info["relres"]})
+            print(f"[apply] n={n} {name}: alpha {a:.4g} omega {w:.3g}: {info['status_str']} "
+                  f"{info['outer_sweeps']} sweeps {info['seconds']:.4f} s", flush=True)
+        g.close()
+    return rows
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sizes", default="8,12,16,24")
+    ap.add_argument("--targets", default="32,64,128")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--maxit", type=int, default=400)
+    ap.add_argument("--maxit-inner", type=int, default=300)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("the GPR study runs on the GPU")
+    dev = torch.device("cuda:0")
+    sizes = [int(s) for s in a.sizes.split(",")]
+    targets = [int(s) for s in a.targets.split(",")]
+    t0 = time.time()
+    train = training(sizes, dev, a.tol, a.maxit, a.maxit_inner)
+    pred = {n: {} for n in targets}
+    table = []
+    for name in ("fp64", "fp32"):
+        rows = [r for r in train if r["prec"] == name and math.isfinite(r["work"])]
+        out = gpr.predict_alpha([r["n"] for r in rows], [r["alpha"] for r in rows], targets, retrain=True)
+        for n, al, sd in out:
+            pred[n][name] = al
+            table.append({"n": n, "train": name, "alpha": al, "sd_log10": sd})
+            print(f"[gpr] {name} training set -> n={n}: alpha {al:.4f} (sd of log10 alpha {sd:.3f})", flush=True)
+    mlp = pr.load() if os.path.exists(pr.WEIGHTS) else None
+    applied = apply(targets, pred, dev, mlp)
+    res = {"training": train, "pred32": table, "apply": applied, "omega": OMEGA, "beta": BETA,
+           "train_tol": a.tol, "wall_seconds": time.time() - t0}
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(res, f, indent=1)
+    print(json.dumps({"wall_seconds": res["wall_seconds"]}))
+
+
+if __name__ == "__main__":
+    main()
