@@ -36,7 +36,8 @@ typedef enum {
   GADI_OK = 0,
   GADI_EINVAL = 1,      /* bad argument or malformed CSR */
   GADI_ENOTSPD = 2,     /* an inner operator showed non-positive curvature */
-  GADI_EOVERFLOW16 = 3, /* a scaled half-precision quantity left the finite range */
+  GADI_EOVERFLOW16 = 3, /* a scaled half-precision quantity left the finite range,
+                           or (FP8 mode) an entry of H or S beyond the E4M3 range */
   GADI_EDIVERGED = 4,   /* non-finite residual or ||r|| > 1e6 ||r_0|| */
   GADI_EMAXIT = 5,      /* outer sweep limit reached */
   GADI_EHIP = 6,        /* a HIP runtime call failed */
@@ -67,14 +68,21 @@ typedef enum { GADI_SPLIT_HSS = 0 } gadi_splitting;
  * compute in fp32; a single-precision u_f computes the residual with an fp32
  * copy of A; a single-precision u stores x in fp32.  The last three modes
  * exist to reproduce the precision study of Section 4.1 (Table 3d); only
- * gadi_ir_solve accepts them (the batched sweep takes the first three). */
+ * gadi_ir_solve accepts them (the batched sweep takes the first three).
+ * GADI_PREC_FP8_IR is the FP8 storage the paper names as future work
+ * (Section 5): the off-diagonal values of H and S in OCP FP8 E4M3 (sign, 4
+ * exponent bits with bias 7, 3 mantissa bits, largest finite 448; rounded to
+ * nearest-even from double once, unscaled), the diagonal of H and the Krylov
+ * vectors in fp16, fp32 arithmetic, double u and u_f.  Entries beyond 448 in
+ * magnitude give EOVERFLOW16 on the first FP8 solve of a handle. */
 typedef enum {
   GADI_PREC_FP64 = 0,    /* (double, double, double): plain GADI               */
   GADI_PREC_FP16_IR = 1, /* (half, double, double)                              */
   GADI_PREC_FP32_IR = 2, /* (single, double, double)                            */
   GADI_PREC_H_D_S = 3,   /* (half, double, single)                              */
   GADI_PREC_H_S_S = 4,   /* (half, single, single)                              */
-  GADI_PREC_S_S_S = 5    /* (single, single, single)                            */
+  GADI_PREC_S_S_S = 5,   /* (single, single, single)                            */
+  GADI_PREC_FP8_IR = 6   /* (fp8 values / half vectors, double, double)          */
 } gadi_precision;
 
 typedef struct {
@@ -152,6 +160,8 @@ gadi_status gadi_ir_solve_batched(gadi_handle* const* hs, int32_t nsys, const do
  *   which = 1: y = (alpha I + H) x   fp16 in/out (half values), fp32 arithmetic
  *   which = 2: y = (I + S / alpha) x fp16 in/out, fp32 arithmetic
  *   which = 3: y = (alpha I + H) x   float64 in/out, float64 operator
+ *   which = 4: y = (alpha I + H) x   fp16 in/out, E4M3 off-diagonal values of H
+ *              (the FP8 mode's operator; the first call encodes them)
  * Enqueued on the bound stream; does not synchronise. */
 gadi_status gadi_spmv(gadi_handle* h, int32_t which, double alpha, const void* x, void* y);
 
@@ -162,6 +172,16 @@ gadi_status gadi_spmv(gadi_handle* h, int32_t which, double alpha, const void* x
  * count through *nnz_out. */
 gadi_status gadi_get_split_fp16(gadi_handle* h, int32_t which, int32_t* out_rp, int32_t* out_col,
                                 uint16_t* out_val, int64_t* nnz_out);
+
+/* Copy the E4M3 codes of the off-diagonal values of H (which = 1) or S
+ * (which = 2), as the FP8 mode stores them, back in CSR order of the union
+ * pattern without the diagonal: out_val[k] for the k-th off-diagonal entry of
+ * row i in ascending column order.  Encodes them first if no FP8 solve or
+ * product has.  out_rp [n+1], out_col, out_val [off-diagonal count] are host
+ * arrays; pass NULL out_col/out_val to query the count through *nnz_out.
+ * EOVERFLOW16 if an entry is beyond the E4M3 range. */
+gadi_status gadi_get_split_fp8(gadi_handle* h, int32_t which, int32_t* out_rp, int32_t* out_col,
+                               uint8_t* out_val, int64_t* nnz_out);
 
 /* Predictor features (the row sums computed on the device from the packed
  * splitting): out[8] = [ln n, dim, log10 mean(beta), log10(max(beta) h/2) with

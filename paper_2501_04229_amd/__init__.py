@@ -17,7 +17,7 @@ from . import build as _build
 LIB_PATH = _build.LIB
 
 OK, EINVAL, ENOTSPD, EOVERFLOW16, EDIVERGED, EMAXIT, EHIP, ENOMEM, EBARRIER = range(9)
-PREC = {"fp64": 0, "fp16": 1, "fp32": 2, "h-d-s": 3, "h-s-s": 4, "s-s-s": 5}
+PREC = {"fp64": 0, "fp16": 1, "fp32": 2, "h-d-s": 3, "h-s-s": 4, "s-s-s": 5, "fp8": 6}
 N_MLP_PARAMS = 4866
 
 
@@ -71,6 +71,7 @@ def _load():
                                         P(SolveInfo)]),
         "gadi_spmv": (i32, [vp, i32, f64, vp, vp]),
         "gadi_get_split_fp16": (i32, [vp, i32, vp, vp, vp, P(i64)]),
+        "gadi_get_split_fp8": (i32, [vp, i32, vp, vp, vp, P(i64)]),
         "gadi_get_layout": (i32, [vp, P(i64)]),
         "gadi_get_phase_profile": (i32, [vp, P(f64), P(i64)]),
         "gadi_features": (i32, [vp, i32, i32, P(f64), P(ctypes.c_float)]),
@@ -215,8 +216,8 @@ class System:
         return x, d
 
     def spmv(self, which: str, x, y, alpha=1.0):
-        """Device product on torch tensors: which in {'A','H16','S16','H64'}."""
-        code = {"A": 0, "H16": 1, "S16": 2, "H64": 3}[which]
+        """Device product on torch tensors: which in {'A','H16','S16','H64','H8'}."""
+        code = {"A": 0, "H16": 1, "S16": 2, "H64": 3, "H8": 4}[which]
         self.bind_current_stream()
         _check(_lib.gadi_spmv(self._h, code, float(alpha), ctypes.c_void_p(x.data_ptr()),
                               ctypes.c_void_p(y.data_ptr())), "gadi_spmv")
@@ -233,6 +234,19 @@ class System:
                                         ctypes.c_void_p(col.ctypes.data), ctypes.c_void_p(val.ctypes.data),
                                         ctypes.byref(nnz)), "split")
         return rp, col, val.view(np.float16)
+
+    def split_fp8(self, which: str):
+        """E4M3 codes of the off-diagonal values of 'H' or 'S' in CSR order of the union pattern."""
+        code = {"H": 1, "S": 2}[which]
+        nnz = ctypes.c_int64(0)
+        _check(_lib.gadi_get_split_fp8(self._h, code, None, None, None, ctypes.byref(nnz)), "split")
+        rp = np.empty(self.n + 1, np.int32)
+        col = np.empty(nnz.value, np.int32)
+        val = np.empty(nnz.value, np.uint8)
+        _check(_lib.gadi_get_split_fp8(self._h, code, ctypes.c_void_p(rp.ctypes.data),
+                                       ctypes.c_void_p(col.ctypes.data), ctypes.c_void_p(val.ctypes.data),
+                                       ctypes.byref(nnz)), "split")
+        return rp, col, val
 
     PHASES = ("residual", "cg_start", "cg_product", "cg_update", "cgne_start", "cgne_product1",
               "cgne_product2", "cgne_update", "x_update")

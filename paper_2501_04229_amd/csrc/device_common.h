@@ -7,13 +7,21 @@
 
 namespace gadi {
 
+// OCP FP8 E4M3 storage: sign, 4 exponent bits (bias 7), 3 mantissa bits; no
+// infinities, largest finite 448.
+struct e4m3 {
+  uint8_t bits;
+};
+
 // Precision modes (u_r, u, u_f) of Algorithm 1.  Inner solves (u_r): MT the
-// stored value type of H and S, VT the stored Krylov vectors, ST the inner
+// stored value type of H and S, DT that of the diagonal of H, VT the stored
+// Krylov vectors, ST the inner
 // solution accumulators, RT the stored outer residual, AT the arithmetic.
 // Outer loop: XT the stored solution x and its update (u), FT the arithmetic
 // of the residual r = b - A x (u_f) and AV the stored values of A it uses.
 struct ModeF16 {  // (half, double, double)
   using MT = __half;
+  using DT = __half;
   using VT = __half;
   using ST = float;
   using RT = float;
@@ -26,6 +34,7 @@ struct ModeF16 {  // (half, double, double)
 };
 struct ModeF32 {  // (single, double, double)
   using MT = float;
+  using DT = float;
   using VT = float;
   using ST = float;
   using RT = float;
@@ -38,6 +47,7 @@ struct ModeF32 {  // (single, double, double)
 };
 struct ModeF64 {  // (double, double, double): plain GADI
   using MT = double;
+  using DT = double;
   using VT = double;
   using ST = double;
   using RT = double;
@@ -65,6 +75,10 @@ struct ModeSSS : ModeF32 {  // (single, single, single)
   using AV = float;
   static constexpr int id = GADI_PREC_S_S_S;
 };
+struct ModeF8 : ModeF16 {  // FP8 values of H and S, half diagonal and vectors; (double, double) outside
+  using MT = e4m3;
+  static constexpr int id = GADI_PREC_FP8_IR;
+};
 
 template <class AT>
 __device__ __forceinline__ AT ld(__half v) {
@@ -77,6 +91,15 @@ __device__ __forceinline__ AT ld(float v) {
 template <class AT>
 __device__ __forceinline__ AT ld(double v) {
   return (AT)v;
+}
+// E4M3 -> AT, exact: the exponent and mantissa fields moved into the binary16
+// fields (exponent field e -> e, mantissa m -> m << 7) give a binary16 value
+// 2^-8 times the E4M3 value, for normal and subnormal codes alike.
+template <class AT>
+__device__ __forceinline__ AT ld(e4m3 v) {
+  const unsigned b = v.bits;
+  const unsigned short h = (unsigned short)(((b & 0x80u) << 8) | ((b & 0x7Fu) << 7));
+  return (AT)(__half2float(__ushort_as_half(h)) * 256.0f);
 }
 
 template <class VT>

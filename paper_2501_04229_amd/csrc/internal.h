@@ -98,6 +98,9 @@ struct System {
   __half* h_off16 = nullptr;
   __half* s_off16 = nullptr;
   __half* h_diag16 = nullptr;
+  uint8_t* h_off8 = nullptr;     // [nslots] E4M3 codes of H and S (FP8 mode), encoded on first use
+  uint8_t* s_off8 = nullptr;
+  int fp8_overflow = 0;          // an entry of H or S is beyond the E4M3 range
   float* h_off32 = nullptr;
   float* s_off32 = nullptr;
   float* h_diag32 = nullptr;
@@ -118,9 +121,9 @@ struct System {
   long long* prof = nullptr;  // [20] per-phase profile of the last solve
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // launch shape of the solve kernel per precision mode, chosen by the autotuner
-  int tuned_block[6] = {0, 0, 0, 0, 0, 0};
-  int tuned_per_cu[6] = {0, 0, 0, 0, 0, 0};
-  int tuned_fused[6] = {0, 0, 0, 0, 0, 0};
+  int tuned_block[7] = {0, 0, 0, 0, 0, 0, 0};
+  int tuned_per_cu[7] = {0, 0, 0, 0, 0, 0, 0};
+  int tuned_fused[7] = {0, 0, 0, 0, 0, 0, 0};
   int last_blocks = 0;
   int last_block_threads = 0;
 };

@@ -63,10 +63,12 @@ static gadi_status upload(T** dst, const std::vector<T>& src) {
   return GADI_OK;
 }
 
+gadi_status ensure_fp8_public(System& s);
+
 void free_system(System& s) {
   void* ptrs[] = {s.slice_dia, s.dia_off, s.slice_ptr, s.col,     s.a_off,   s.a_diag,  s.h_off64, s.s_off64, s.h_diag64,
                   s.h_off16,   s.s_off16, s.h_diag16, s.h_off32, s.s_off32, s.h_diag32, s.a_off32, s.a_diag32, s.ws,
-                  s.hist,      s.sync,    s.flags,   s.part,    s.result,  s.info, s.prof};
+                  s.hist,      s.sync,    s.flags,   s.part,    s.result,  s.info, s.prof, s.h_off8, s.s_off8};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (s.ev0) (void)hipEventDestroy(s.ev0);
@@ -437,6 +439,39 @@ extern "C" gadi_status gadi_get_split_fp16(gadi_handle* h, int32_t which, int32_
         out_val[pos] = vj;
         ++pos;
       }
+    }
+    out_rp[i + 1] = (int32_t)pos;
+  }
+  return GADI_OK;
+}
+
+extern "C" gadi_status gadi_get_split_fp8(gadi_handle* h, int32_t which, int32_t* out_rp, int32_t* out_col,
+                                          uint8_t* out_val, int64_t* nnz_out) {
+  if (!h || (which != 1 && which != 2)) return GADI_EINVAL;
+  System& S = h->sys;
+  if (nnz_out) *nnz_out = S.nnz_off;
+  if (!out_rp && !out_col && !out_val) return GADI_OK;
+  if (!out_rp || !out_col || !out_val) return GADI_EINVAL;
+  GADI_HIP_CHECK(hipSetDevice(S.device));
+  const gadi_status st = ensure_fp8_public(S);
+  if (st != GADI_OK) return st;
+  std::vector<int32_t> sp(S.nslices + 1), c(S.nslots);
+  std::vector<uint8_t> v(S.nslots);
+  GADI_HIP_CHECK(hipMemcpy(sp.data(), S.slice_ptr, sp.size() * 4, hipMemcpyDeviceToHost));
+  GADI_HIP_CHECK(hipMemcpy(c.data(), S.col, c.size() * 4, hipMemcpyDeviceToHost));
+  GADI_HIP_CHECK(hipMemcpy(v.data(), which == 1 ? S.h_off8 : S.s_off8, v.size(), hipMemcpyDeviceToHost));
+  // slots of a row hold its off-diagonal entries in ascending column order
+  int64_t pos = 0;
+  out_rp[0] = 0;
+  for (int i = 0; i < S.n; ++i) {
+    const int s = i / kSlice, l = i % kSlice;
+    const int w = (sp[s + 1] - sp[s]) / kSlice;
+    for (int j = 0; j < w; ++j) {
+      const int64_t k = sp[s] + (int64_t)j * kSlice + l;
+      if (c[k] == i || c[k] < 0) continue;  // padding or phantom
+      out_col[pos] = c[k];
+      out_val[pos] = v[k];
+      ++pos;
     }
     out_rp[i + 1] = (int32_t)pos;
   }

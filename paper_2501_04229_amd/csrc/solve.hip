@@ -151,6 +151,65 @@ __global__ void fill_zero_kernel(double* __restrict__ p, long long n) {
 
 gadi_status ensure_fp32_public(System& s) { return ensure_fp32(s); }
 
+// E4M3 code of v, rounded to nearest-even in one step from double; `over` is
+// set when |v| is beyond 464 (448 plus half its spacing) or not finite.  Within
+// the binade [2^E, 2^(E+1)) the spacing is 2^(E-3); the subnormals share the
+// spacing 2^-9 of the lowest binade E = -6.  With N = |v| / 2^(E-3) rounded
+// (8..16, or 0..16 at E = -6) the code is 8 (E + 6) + N: N = 16 carries into
+// the next binade's first code.
+__device__ __forceinline__ uint8_t e4m3_rne(double v, bool& over) {
+  const unsigned sign = signbit(v) ? 0x80u : 0u;
+  const double a = fabs(v);
+  if (!(a <= 464.0)) {
+    over = true;
+    return (uint8_t)(sign | 0x7Eu);
+  }
+  if (a == 0.0) return (uint8_t)sign;
+  int k;
+  (void)frexp(a, &k);  // a = f 2^k, f in [1/2, 1)
+  int E = k - 1;
+  if (E < -6) E = -6;
+  const double N = rint(ldexp(a, 3 - E));
+  const unsigned code = (unsigned)(8 * (E + 6)) + (unsigned)N;
+  return (uint8_t)(sign | (code > 0x7Eu ? 0x7Eu : code));
+}
+
+__global__ void encode_e4m3_kernel(const double* __restrict__ in, uint8_t* __restrict__ out, long long n,
+                                   unsigned* __restrict__ over) {
+  bool o = false;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = e4m3_rne(in[i], o);
+  if (o) atomicOr(over, 1u);
+}
+
+// E4M3 copies of the off-diagonal values of H and S for the FP8 mode, encoded
+// once per handle from the double splitting (synchronises the stream).
+static gadi_status ensure_fp8(System& s) {
+  if (s.h_off8) return s.fp8_overflow ? GADI_EOVERFLOW16 : GADI_OK;
+  const size_t n = s.nslots ? (size_t)s.nslots : 1;
+  uint8_t *h8 = nullptr, *s8 = nullptr;
+  unsigned* over = nullptr;
+  GADI_HIP_CHECK(hipMalloc((void**)&h8, n));
+  GADI_HIP_CHECK(hipMalloc((void**)&s8, n));
+  GADI_HIP_CHECK(hipMalloc((void**)&over, sizeof(unsigned)));
+  GADI_HIP_CHECK(hipMemsetAsync(over, 0, sizeof(unsigned), s.stream));
+  if (s.nslots) {
+    hipLaunchKernelGGL(encode_e4m3_kernel, dim3(1024), dim3(256), 0, s.stream, s.h_off64, h8, (long long)s.nslots, over);
+    hipLaunchKernelGGL(encode_e4m3_kernel, dim3(1024), dim3(256), 0, s.stream, s.s_off64, s8, (long long)s.nslots, over);
+  }
+  GADI_HIP_CHECK(hipGetLastError());
+  unsigned flag = 0;
+  GADI_HIP_CHECK(hipMemcpyAsync(&flag, over, sizeof(unsigned), hipMemcpyDeviceToHost, s.stream));
+  GADI_HIP_CHECK(hipStreamSynchronize(s.stream));
+  GADI_HIP_CHECK(hipFree(over));
+  s.h_off8 = h8;
+  s.s_off8 = s8;
+  s.fp8_overflow = flag != 0;
+  return s.fp8_overflow ? GADI_EOVERFLOW16 : GADI_OK;
+}
+
+gadi_status ensure_fp8_public(System& s) { return ensure_fp8(s); }
+
 template <class Mode, int BLOCK, bool FUSED, int PW>
 static gadi_status launch_t(System& s, SolveArgs a, int per_cu) {
   int nb = 0;
@@ -177,7 +236,8 @@ static gadi_status launch_block(System& s, const SolveArgs& a, int block, int pe
   switch (block) {
     case 512:
       // the precision-study modes are built in one block size only
-      if constexpr (Mode::id <= GADI_PREC_FP32_IR) return launch_t<Mode, 512, FUSED, PW>(s, a, per_cu);
+      if constexpr (Mode::id <= GADI_PREC_FP32_IR || Mode::id == GADI_PREC_FP8_IR)
+        return launch_t<Mode, 512, FUSED, PW>(s, a, per_cu);
       return GADI_EINVAL;
     case 1024: return launch_t<Mode, 1024, FUSED, PW>(s, a, per_cu);
   }
@@ -203,6 +263,7 @@ static gadi_status launch_prec(System& s, int prec, const SolveArgs& a, int bloc
     case GADI_PREC_H_D_S: return launch_mode<ModeHDS, FUSED>(s, a, block, per_cu);
     case GADI_PREC_H_S_S: return launch_mode<ModeHSS, FUSED>(s, a, block, per_cu);
     case GADI_PREC_S_S_S: return launch_mode<ModeSSS, FUSED>(s, a, block, per_cu);
+    case GADI_PREC_FP8_IR: return launch_mode<ModeF8, FUSED>(s, a, block, per_cu);
   }
   return launch_mode<ModeF64, FUSED>(s, a, block, per_cu);
 }
@@ -214,7 +275,9 @@ static gadi_status launch_solve(System& s, int prec, const SolveArgs& a, int blo
 // solution stored in single precision (u = single)
 static bool single_solution(int prec) { return prec == GADI_PREC_H_S_S || prec == GADI_PREC_S_S_S; }
 // residual in single precision (u_f = single)
-static bool single_residual(int prec) { return prec >= GADI_PREC_H_D_S; }
+static bool single_residual(int prec) {
+  return prec == GADI_PREC_H_D_S || prec == GADI_PREC_H_S_S || prec == GADI_PREC_S_S_S;
+}
 
 // Autotuner: time three outer sweeps from x = 0 in every candidate (threads
 // per block x blocks per compute unit x inner-solver variant), after one
@@ -300,7 +363,7 @@ extern "C" gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x,
   gadi_options o;
   if (opts) o = *opts;
   else gadi_default_options(&o, GADI_PREC_FP16_IR);
-  if (o.prec < GADI_PREC_FP64 || o.prec > GADI_PREC_S_S_S || !(o.eps_inner > 0.0) || o.eps_inner >= 1.0 ||
+  if (o.prec < GADI_PREC_FP64 || o.prec > GADI_PREC_FP8_IR || !(o.eps_inner > 0.0) || o.eps_inner >= 1.0 ||
       o.maxit_outer < 0 || o.maxit_inner < 1)
     return GADI_EINVAL;
   System& s = h->sys;
@@ -310,6 +373,10 @@ extern "C" gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x,
   const bool inner32 = o.prec == GADI_PREC_FP32_IR || o.prec == GADI_PREC_S_S_S;
   if (inner32 && (st = ensure_fp32(s)) != GADI_OK) return st;
   if (single_residual(o.prec) && (st = ensure_a32(s)) != GADI_OK) return st;
+  if (o.prec == GADI_PREC_FP8_IR && (st = ensure_fp8(s)) != GADI_OK) {
+    if (info) info->status = st;
+    return st;
+  }
   if (o.record_history) {
     int cap = o.maxit_outer + 1;
     if (cap > s.hist_cap) {
@@ -364,6 +431,10 @@ extern "C" gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x,
   if (o.prec == GADI_PREC_FP16_IR || o.prec == GADI_PREC_H_D_S || o.prec == GADI_PREC_H_S_S) {
     a.h_off = s.h_off16;
     a.s_off = s.s_off16;
+    a.h_diag = s.h_diag16;
+  } else if (o.prec == GADI_PREC_FP8_IR) {
+    a.h_off = s.h_off8;
+    a.s_off = s.s_off8;
     a.h_diag = s.h_diag16;
   } else if (inner32) {
     a.h_off = s.h_off32;

@@ -311,7 +311,8 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
 
   const MT* __restrict__ hoff = (const MT*)a.h_off;
   const MT* __restrict__ soff = (const MT*)a.s_off;
-  const MT* __restrict__ hdiag = (const MT*)a.h_diag;
+  using DT = typename Mode::DT;
+  const DT* __restrict__ hdiag = (const DT*)a.h_diag;
   RT* __restrict__ r = (RT*)a.r;
   ST* __restrict__ z = (ST*)a.z;
   ST* __restrict__ wsol = (ST*)a.w;
@@ -430,7 +431,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
             [&](unsigned row) {
               struct {
                 RT rr;
-                MT hd;
+                DT hd;
                 decltype(pat.gather(0u, hoff, gr)) g;
               } l{at(r, row), at(hdiag, row), pat.gather(row, hoff, gr)};
               return l;
@@ -491,7 +492,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                 [&](unsigned row) {
                   struct {
                     VT r, w;
-                    MT hd;
+                    DT hd;
                     decltype(pat.gather(0u, hoff, gl)) g;
                   } l{at(rk, row), at(wk, row), at(hdiag, row), pat.gather(row, hoff, gl)};
                   return l;
@@ -520,7 +521,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                   struct {
                     VT r, w, sp, p;
                     ST z;
-                    MT hd;
+                    DT hd;
                     decltype(pat.gather(0u, hoff, gl)) g;
                   } l{at(rk, row), at(wk, row), at(sprev, row), at(P, row), at(z, row), at(hdiag, row), pat.gather(row, hoff, gl)};
                   return l;
@@ -562,7 +563,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
             [&](unsigned row) {
               struct {
                 RT rr;
-                MT hd;
+                DT hd;
                 decltype(pat.gather(0u, hoff, gr)) g;
               } l{at(r, row), at(hdiag, row), pat.gather(row, hoff, gr)};
               return l;
@@ -643,7 +644,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                 [&](unsigned row) {
                   struct {
                     VT r, p, q;
-                    MT hd;
+                    DT hd;
                     decltype(pat.gather(0u, hoff, gv)) g;
                   } l{at(vr, row), at(vp, row), at(vq, row), at(hdiag, row), pat.gather(row, hoff, gv)};
                   return l;

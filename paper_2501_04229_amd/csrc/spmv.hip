@@ -7,6 +7,8 @@
 
 namespace gadi {
 
+gadi_status ensure_fp8_public(System& s);
+
 // The products run the solver's row loop (solve_body.h): every load of U
 // tiles of BLOCK rows is issued before their arithmetic, under the same
 // pattern policies (uniform diagonal layout: offsets in scalar registers).
@@ -40,26 +42,27 @@ __global__ void __launch_bounds__(kSpmvBlock) spmv_a64_kernel(Pat pat, const dou
 }
 
 // y = (alpha I + H) x with H, x, y in the value type MT, arithmetic in AT
-template <int U, class Pat, class MT, class AT>
+// y = (alpha I + H) x: off-diagonal values MT, diagonal and vectors VT
+template <int U, class Pat, class MT, class VT, class AT>
 __global__ void __launch_bounds__(kSpmvBlock) spmv_h_kernel(Pat pat, const MT* __restrict__ off,
-                                                           const MT* __restrict__ diag, const MT* __restrict__ x,
-                                                           MT* __restrict__ y, AT alpha, int n, int ntiles) {
+                                                           const VT* __restrict__ diag, const VT* __restrict__ x,
+                                                           VT* __restrict__ y, AT alpha, int n, int ntiles) {
   const int t0 = blockIdx.x * U, t1 = t0 + U < ntiles ? t0 + U : ntiles;
   auto gx = [&](unsigned c) { return at(x, c); };
   for_rows<kSpmvBlock, U>(
       t0, t1,
       [&](unsigned row) {
         struct {
-          MT d, xr;
+          VT d, xr;
           decltype(pat.gather(0u, off, gx)) g;
         } l{at(diag, row), at(x, row < (unsigned)n ? row : (unsigned)n - 1u), pat.gather(row, off, gx)};
         return l;
       },
       [&](const auto& l) {
-        return (alpha + ld<AT>(l.d)) * ld<AT>(l.xr) + pat.template dot<AT>(l.g, [](MT v) { return ld<AT>(v); });
+        return (alpha + ld<AT>(l.d)) * ld<AT>(l.xr) + pat.template dot<AT>(l.g, [](VT v) { return ld<AT>(v); });
       },
       [&](unsigned row, AT v) {
-        if (row < (unsigned)n) at(y, row) = st<MT>(v);
+        if (row < (unsigned)n) at(y, row) = st<VT>(v);
       });
 }
 
@@ -145,7 +148,7 @@ static void launch_products(System& s, const Pat& pat, int which, double alpha, 
                          (const double*)x, (double*)y, s.n, ntiles);
       break;
     case 1:
-      hipLaunchKernelGGL((spmv_h_kernel<U16, Pat, __half, float>), g16, block, 0, s.stream, pat, s.h_off16,
+      hipLaunchKernelGGL((spmv_h_kernel<U16, Pat, __half, __half, float>), g16, block, 0, s.stream, pat, s.h_off16,
                          s.h_diag16, (const __half*)x, (__half*)y, (float)alpha, s.n, ntiles);
       break;
     case 2:
@@ -153,8 +156,12 @@ static void launch_products(System& s, const Pat& pat, int which, double alpha, 
                          (__half*)y, (float)(1.0 / alpha), s.n, ntiles);
       break;
     case 3:
-      hipLaunchKernelGGL((spmv_h_kernel<U64, Pat, double, double>), g64, block, 0, s.stream, pat, s.h_off64,
+      hipLaunchKernelGGL((spmv_h_kernel<U64, Pat, double, double, double>), g64, block, 0, s.stream, pat, s.h_off64,
                          s.h_diag64, (const double*)x, (double*)y, alpha, s.n, ntiles);
+      break;
+    case 4:
+      hipLaunchKernelGGL((spmv_h_kernel<U16, Pat, e4m3, __half, float>), g16, block, 0, s.stream, pat,
+                         (const e4m3*)s.h_off8, s.h_diag16, (const __half*)x, (__half*)y, (float)alpha, s.n, ntiles);
       break;
   }
 }
@@ -168,10 +175,14 @@ static PatDia<W> uniform_pattern(const System& s) {
 }
 
 extern "C" gadi_status gadi_spmv(gadi_handle* h, int32_t which, double alpha, const void* x, void* y) {
-  if (!h || !x || !y || which < 0 || which > 3) return GADI_EINVAL;
-  if ((which == 1 || which == 2 || which == 3) && !(alpha > 0.0)) return GADI_EINVAL;
+  if (!h || !x || !y || which < 0 || which > 4) return GADI_EINVAL;
+  if (which != 0 && !(alpha > 0.0)) return GADI_EINVAL;
   System& s = h->sys;
   GADI_HIP_CHECK(hipSetDevice(s.device));
+  if (which == 4) {
+    const gadi_status st = ensure_fp8_public(s);
+    if (st != GADI_OK) return st;
+  }
   switch (s.dia_uniform) {
     case 4: launch_products<2, 2>(s, uniform_pattern<4>(s), which, alpha, x, y); break;
     case 6: launch_products<2, 2>(s, uniform_pattern<6>(s), which, alpha, x, y); break;
