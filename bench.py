@@ -278,6 +278,19 @@ def main():
                 "rel_diff_vs_fp16ir": float(np.linalg.norm(xh - x64h) / np.linalg.norm(x64h))}
         print(f"# fp64 GADI: {i64['seconds']:.3f}s sweeps={i64['outer_sweeps']} inner_H={i64['inner_H']} "
               f"inner_S={i64['inner_S']} relres={i64['relres']:.3e}", file=sys.stderr, flush=True)
+        # the same plain FP64 GADI with the reduced-precision solve's inner tolerance: separates the
+        # effect of the precision from that of the inner tolerance (informational)
+        eps_rp = gadi.options(args.prec).eps_inner
+        torch.cuda.synchronize()
+        tf0 = time.perf_counter()
+        _, i64e, _, _ = run("fp64", 0.5, 0.5, eps_rp)
+        torch.cuda.synchronize()
+        fp64["same_inner_eps"] = {"eps_inner": eps_rp, "seconds": i64e["seconds"],
+                                  "wall_seconds": time.perf_counter() - tf0, "status": i64e["status_str"],
+                                  "sweeps": i64e["outer_sweeps"], "inner_H": i64e["inner_H"],
+                                  "inner_S": i64e["inner_S"]}
+        print(f"# fp64 GADI, inner {eps_rp:g}: {i64e['seconds']:.3f}s sweeps={i64e['outer_sweeps']}",
+              file=sys.stderr, flush=True)
     sp = spmv_gbs(g, A, alpha)
     print(f"# spmv: {sp}", file=sys.stderr, flush=True)
 
@@ -304,7 +317,7 @@ def main():
         "data": "synthetic",
         "layout": lay,
         "config": {"workload": args.workload, "N": n, "nnz": z, "tol": 1e-10,
-                   "eps_inner": eps if eps is not None else (1e-6 if args.prec == "fp64" else 1e-3),
+                   "eps_inner": eps if eps is not None else gadi.options(args.prec).eps_inner,
                    "alpha_predicted": alpha, "omega_predicted": omega, "params": psrc, "used": used,
                    "prec": args.prec,
                    "solve_launch_blocks_threads": list(g.solver_blocks())},

@@ -116,8 +116,9 @@ typedef struct {
 typedef struct gadi_handle gadi_handle;
 typedef struct gadi_mlp gadi_mlp;
 
-/* Fill `o` with defaults for `prec`: eps_inner 1e-6 (FP64) or 1e-3 (FP16/FP32),
- * maxit_outer 20000, maxit_inner 2000, host pointers, no history, no pruning. */
+/* Fill `o` with defaults for `prec`: eps_inner 1e-6 (FP64) or 3e-2 (every
+ * reduced-precision mode), maxit_outer 20000, maxit_inner 2000, host pointers,
+ * no history, no pruning. */
 void gadi_default_options(gadi_options* o, gadi_precision prec);
 
 /* Validate A, form H and S (Section 4.1 splitting) on the union pattern of A and

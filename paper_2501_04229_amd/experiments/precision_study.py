@@ -44,7 +44,7 @@ def attainable(g, b, al, omega, prec, chunk, budget, seconds, tol=1e-15):
     `budget` sweeps or `seconds` of device time have been spent (then the
     result is marked budget-limited).  RES stays relative to ||b|| across
     launches (each launch reports it relative to its own start)."""
-    eps = 1e-6 if prec == "fp64" else None
+    eps = 1e-6 if prec == "fp64" else 1e-3
     x, scale, best, at, done, status, secs, limited = None, 1.0, math.inf, 0, 0, "ok", 0.0, False
     while True:
         if done >= budget or secs >= seconds:
