@@ -170,6 +170,7 @@ def main():
     ap.add_argument("--params", default="mlp", choices=["mlp", "default"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-spmv", action="store_true", help="skip the stand-alone product timing (graph replays)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with one elementwise copy of 2^26 floats (reads and writes 256 MiB) "
                          "to calibrate hardware byte counters")
@@ -291,8 +292,10 @@ def main():
                                   "inner_S": i64e["inner_S"]}
         print(f"# fp64 GADI, inner {eps_rp:g}: {i64e['seconds']:.3f}s sweeps={i64e['outer_sweeps']}",
               file=sys.stderr, flush=True)
-    sp = spmv_gbs(g, A, alpha)
-    print(f"# spmv: {sp}", file=sys.stderr, flush=True)
+    sp = None
+    if not args.no_spmv:
+        sp = spmv_gbs(g, A, alpha)
+        print(f"# spmv: {sp}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu:
