@@ -37,6 +37,19 @@ def kernel_table(c, limit=12):
     return "\n".join(out)
 
 
+def by_grid(c, substr):
+    """Launches of kernels matching substr grouped by (kernel, launch grid): calls and mean duration, so that
+    runs of one kernel at several problem sizes in one trace stay apart."""
+    rows = c.execute("select name, grid_x * grid_y * grid_z, workgroup_x, count(*), avg(duration), sum(duration) "
+                     "from kernels where name like ? group by name, grid_x, grid_y, grid_z, workgroup_x "
+                     "order by grid_x * grid_y * grid_z, sum(duration) desc", (f"%{substr}%",)).fetchall()
+    out = ["| kernel | grid threads | block | calls | mean us | total ms |", "|---|---|---|---|---|---|"]
+    for name, grid, block, calls, avg, tot in rows:
+        short = name.split("(")[0].replace("void ", "")
+        out.append(f"| `{short}` | {grid} | {block} | {calls} | {avg / 1e3:.1f} | {tot / 1e6:.3f} |")
+    return "\n".join(out)
+
+
 def launches(c, substr, min_ms, timed=0):
     # kernels reports nanoseconds
     rows = c.execute("select name, duration, grid_x, workgroup_x, vgpr_count from kernels where name like ? "
@@ -155,6 +168,8 @@ def main():
     ap.add_argument("--kernel", default="solve_kernel")
     ap.add_argument("--min-ms", type=float, default=0.0)
     ap.add_argument("--copy-bytes", type=float, default=0.0)
+    ap.add_argument("--by-grid", action="store_true",
+                    help="kernel trace: group the matching launches by kernel and launch grid")
     a = ap.parse_args()
     if a.traffic:
         print(traffic(a.traffic[0], a.traffic[1], a.kernel, a.launches, a.copy_bytes))
@@ -166,6 +181,9 @@ def main():
     has_trace = c.execute("select count(*) from kernels").fetchone()[0] > 0 if "kernels" in views else False
     has_pmc = c.execute("select count(*) from counters_collection").fetchone()[0] > 0 \
         if "counters_collection" in views else False
+    if has_trace and a.by_grid:
+        print(by_grid(c, a.kernel))
+        return
     if has_trace and "top_kernels" in views:
         print(kernel_table(c))
         print()
