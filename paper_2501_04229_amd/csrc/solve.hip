@@ -189,19 +189,31 @@ static gadi_status ensure_fp8(System& s) {
   const size_t n = s.nslots ? (size_t)s.nslots : 1;
   uint8_t *h8 = nullptr, *s8 = nullptr;
   unsigned* over = nullptr;
-  GADI_HIP_CHECK(hipMalloc((void**)&h8, n));
-  GADI_HIP_CHECK(hipMalloc((void**)&s8, n));
-  GADI_HIP_CHECK(hipMalloc((void**)&over, sizeof(unsigned)));
-  GADI_HIP_CHECK(hipMemsetAsync(over, 0, sizeof(unsigned), s.stream));
-  if (s.nslots) {
-    hipLaunchKernelGGL(encode_e4m3_kernel, dim3(1024), dim3(256), 0, s.stream, s.h_off64, h8, (long long)s.nslots, over);
-    hipLaunchKernelGGL(encode_e4m3_kernel, dim3(1024), dim3(256), 0, s.stream, s.s_off64, s8, (long long)s.nslots, over);
-  }
-  GADI_HIP_CHECK(hipGetLastError());
   unsigned flag = 0;
-  GADI_HIP_CHECK(hipMemcpyAsync(&flag, over, sizeof(unsigned), hipMemcpyDeviceToHost, s.stream));
-  GADI_HIP_CHECK(hipStreamSynchronize(s.stream));
-  GADI_HIP_CHECK(hipFree(over));
+  // every exit below frees what this call allocated unless it is kept
+  auto encode = [&]() -> gadi_status {
+    GADI_HIP_CHECK(hipMalloc((void**)&h8, n));
+    GADI_HIP_CHECK(hipMalloc((void**)&s8, n));
+    GADI_HIP_CHECK(hipMalloc((void**)&over, sizeof(unsigned)));
+    GADI_HIP_CHECK(hipMemsetAsync(over, 0, sizeof(unsigned), s.stream));
+    if (s.nslots) {
+      hipLaunchKernelGGL(encode_e4m3_kernel, dim3(1024), dim3(256), 0, s.stream, s.h_off64, h8, (long long)s.nslots,
+                         over);
+      hipLaunchKernelGGL(encode_e4m3_kernel, dim3(1024), dim3(256), 0, s.stream, s.s_off64, s8, (long long)s.nslots,
+                         over);
+    }
+    GADI_HIP_CHECK(hipGetLastError());
+    GADI_HIP_CHECK(hipMemcpyAsync(&flag, over, sizeof(unsigned), hipMemcpyDeviceToHost, s.stream));
+    GADI_HIP_CHECK(hipStreamSynchronize(s.stream));
+    return GADI_OK;
+  };
+  const gadi_status st = encode();
+  if (over) (void)hipFree(over);
+  if (st != GADI_OK) {
+    if (h8) (void)hipFree(h8);
+    if (s8) (void)hipFree(s8);
+    return st;
+  }
   s.h_off8 = h8;
   s.s_off8 = s8;
   s.fp8_overflow = flag != 0;
