@@ -305,7 +305,7 @@ gadi_status gadi_sylv_destroy(gadi_sylv* h);
  * y = log10 alpha. */
 typedef struct gadi_gpr gadi_gpr;
 
-/* Fit to m points (host arrays x[m], y[m], finite; 1 <= m <= 4096).  On
+/* Fit to m points (host arrays x[m], y[m], finite; 1 <= m <= 256).  On
  * success *out owns the model.  EINVAL for bad arguments or when no grid point
  * gives a positive definite kernel matrix. */
 gadi_status gadi_gpr_fit(const double* x, const double* y, int32_t m, gadi_gpr** out);

@@ -79,7 +79,8 @@ double kern(double a, double b, double ell) {
 extern "C" gadi_status gadi_gpr_fit(const double* x, const double* y, int32_t m, gadi_gpr** out) {
   if (!out) return GADI_EINVAL;
   *out = nullptr;
-  if (!x || !y || m < 1 || m > 4096) return GADI_EINVAL;
+  // the grid search factors 325 m x m matrices: O(100 m^3) flops, about a second at the limit
+  if (!x || !y || m < 1 || m > 256) return GADI_EINVAL;
   for (int i = 0; i < m; ++i)
     if (!std::isfinite(x[i]) || !std::isfinite(y[i])) return GADI_EINVAL;
   gadi_gpr* g = new (std::nothrow) gadi_gpr();

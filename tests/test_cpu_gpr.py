@@ -47,6 +47,8 @@ def test_argument_checks():
         gpr.GPR(np.array([1.0, np.nan]), np.array([0.0, 1.0]))
     with pytest.raises(ValueError):
         gpr.GPR(np.array([1.0, 2.0]), np.array([0.0]))
+    with pytest.raises(gadi.GadiError):
+        gpr.GPR(np.arange(257.0), np.zeros(257))
 
 
 def test_retraining_adds_each_prediction():
