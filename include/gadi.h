@@ -162,7 +162,8 @@ gadi_status gadi_ir_solve_batched(gadi_handle* const* hs, int32_t nsys, const do
  *   which = 2: y = (I + S / alpha) x fp16 in/out, fp32 arithmetic
  *   which = 3: y = (alpha I + H) x   float64 in/out, float64 operator
  *   which = 4: y = (alpha I + H) x   fp16 in/out, E4M3 off-diagonal values of H
- *              (the FP8 mode's operator; the first call encodes them)
+ *              (the FP8 mode's operator; the first FP8 call on a handle encodes
+ *              them, which allocates and synchronises: not under graph capture)
  * Enqueued on the bound stream; does not synchronise. */
 gadi_status gadi_spmv(gadi_handle* h, int32_t which, double alpha, const void* x, void* y);
 
