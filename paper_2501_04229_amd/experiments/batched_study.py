@@ -1,16 +1,17 @@
 """Batched (alpha, omega) sweep throughput (the training-set generation of Section 3.3).
 
-    python -m paper_2501_04229_amd.experiments.batched_study [--count 64] [--sequential 4]
+    python -m paper_2501_04229_amd.experiments.batched_study [--count 64] [--group 16] [--sequential 4]
 
-The batched family (64 uneven 2-D convection-diffusion systems, n ~ U{128..1024},
+The batched family (uneven 2-D convection-diffusion systems, n ~ U{128..1024},
 beta ~ logU(1, 1000), seed 2, b = A 1) swept over the 16 (alpha, omega) trials
-(4 log-spaced alphas in [1e-3, 10] x omega in {0, 0.5, 1, 1.5}) in one
-persistent launch, FP16-IR to RES 1e-10, at most 5000 sweeps per trial.
-Reported: wall time of the launch, trials per second, sweeps per second,
-converged / censored trials; then the same trials of the `sequential`
-smallest systems solved one by one with gadi_ir_solve for the speed-up of batching
-(sweep counts must agree within max(2, 2%)), with and without the pruning of
-dominated trials.
+(4 log-spaced alphas in [1e-3, 10] x omega in {0, 0.5, 1, 1.5}), FP16-IR to
+RES 1e-10, at most 5000 sweeps per trial, with dominated trials pruned (a trial
+stops once its work exceeds that of a converged trial of its system).  The
+family runs in launches of `group` systems (16 x 16 = 256 units, one per
+compute unit), each reported when it ends: wall time, trials per second,
+sweeps per second, converged trials.  Then the `sequential` smallest systems:
+one unpruned batched launch against the same trials solved one by one with
+gadi_ir_solve (records must agree: status, sweeps within max(2, 2%)).
 """
 from __future__ import annotations
 
@@ -29,9 +30,20 @@ import paper_2501_04229_amd as gadi  # noqa: E402
 from paper_2501_04229_amd import predictor as pr  # noqa: E402
 
 
+def build(fam):
+    systems, bs = [], []
+    for n, dim, beta in fam:
+        A = gi.convdiff(n, dim, beta)
+        _, b = gi.rhs_for(A, "ones")
+        systems.append(gadi.System(A))
+        bs.append(b)
+    return systems, bs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--count", type=int, default=64)
+    ap.add_argument("--group", type=int, default=16)
     ap.add_argument("--sequential", type=int, default=4)
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
@@ -39,50 +51,63 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("the batched study runs on the GPU")
     fam = gi.batched_family(a.count)
-    systems, bs = [], []
-    for n, dim, beta in fam:
-        A = gi.convdiff(n, dim, beta)
-        _, b = gi.rhs_for(A, "ones")
-        systems.append(gadi.System(A))
-        bs.append(b)
-    rows = sum(s.n for s in systems)
     al, om = pr.trial_grid()
-    res = {"systems": len(systems), "rows": rows, "trials_per_system": len(al)}
-    full = None
-    for prune in (True, False):
-        gadi.solve_batched(systems[:2], bs[:2], al, om, tol=1e-10, maxit_outer=50, prune=prune)  # tune, warm up
+    res = {"systems": len(fam), "trials_per_system": len(al), "groups": []}
+    tot_t, tot_trials, tot_sweeps, tot_ok, tot_rows = 0.0, 0, 0, 0, 0
+    for g0 in range(0, len(fam), a.group):
+        t0 = time.perf_counter()
+        systems, bs = build(fam[g0:g0 + a.group])
+        t_setup = time.perf_counter() - t0
+        rows = sum(s.n for s in systems)
+        gadi.solve_batched(systems[:1], bs[:1], al, om, tol=1e-10, maxit_outer=20, prune=True)  # tuner, warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        recs, _ = gadi.solve_batched(systems, bs, al, om, tol=1e-10, maxit_outer=5000, prune=prune)
+        recs, _ = gadi.solve_batched(systems, bs, al, om, tol=1e-10, maxit_outer=5000, prune=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         flat = [r for rs in recs for r in rs]
         ok = sum(r["status"] == gadi.OK for r in flat)
         sweeps = sum(r["outer_sweeps"] for r in flat)
-        key = "pruned" if prune else "full"
-        res[key] = {"seconds": dt, "trials": len(flat), "converged": ok, "sweeps": sweeps,
-                    "trials_per_s": len(flat) / dt, "sweeps_per_s": sweeps / dt}
-        print(f"[batched {key}] {len(flat)} trials over {len(systems)} systems ({rows} rows): {dt:.3f} s, "
-              f"{len(flat) / dt:.1f} trials/s, {sweeps / dt:.0f} sweeps/s, {ok} converged", flush=True)
-        if not prune:
-            full = recs
-    k = min(a.sequential, len(systems))
-    smallest = sorted(range(len(systems)), key=lambda i: systems[i].n)[:k]
+        res["groups"].append({"first": g0, "systems": len(systems), "rows": rows, "seconds": dt, "setup_s": t_setup,
+                              "trials": len(flat), "converged": ok, "sweeps": sweeps})
+        tot_t += dt
+        tot_trials += len(flat)
+        tot_sweeps += sweeps
+        tot_ok += ok
+        tot_rows += rows
+        print(f"[batched] systems {g0}..{g0 + len(systems) - 1} ({rows} rows): {len(flat)} trials in {dt:.3f} s, "
+              f"{len(flat) / dt:.1f} trials/s, {sweeps / dt:.0f} sweeps/s, {ok} converged (setup {t_setup:.1f} s)",
+              flush=True)
+        for s in systems:
+            s.close()
+    res["total"] = {"seconds": tot_t, "trials": tot_trials, "converged": tot_ok, "sweeps": tot_sweeps,
+                    "rows": tot_rows, "trials_per_s": tot_trials / tot_t, "sweeps_per_s": tot_sweeps / tot_t}
+    print(f"[batched total] {tot_trials} trials, {tot_rows} rows: {tot_t:.3f} s, {tot_trials / tot_t:.1f} trials/s, "
+          f"{tot_ok} converged", flush=True)
+
+    small = sorted(fam, key=lambda f: f[0])[:a.sequential]
+    systems, bs = build(small)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    agree, seq_sweeps = 0, 0
-    for s in smallest:
+    recs, _ = gadi.solve_batched(systems, bs, al, om, tol=1e-10, maxit_outer=5000, prune=False)
+    torch.cuda.synchronize()
+    dt_b = time.perf_counter() - t0
+    print(f"[batched unpruned] the {len(systems)} smallest systems: {dt_b:.3f} s", flush=True)
+    t0 = time.perf_counter()
+    agree = 0
+    for s in range(len(systems)):
         for t in range(len(al)):
             _, info = systems[s].solve(bs[s], al[t], om[t], tol=1e-10, maxit_outer=5000)
-            seq_sweeps += info["outer_sweeps"]
-            rb = full[s][t]
+            rb = recs[s][t]
             if info["status"] == rb["status"] and abs(info["outer_sweeps"] - rb["outer_sweeps"]) <= max(
                     2, 0.02 * info["outer_sweeps"]):
                 agree += 1
-    dt_seq = time.perf_counter() - t0
-    res["sequential"] = {"systems": k, "seconds": dt_seq, "sweeps": seq_sweeps, "records_agree": agree,
-                         "trials": k * len(al), "rows": sum(systems[i].n for i in smallest)}
-    print(f"[sequential] the {k} smallest systems, {k * len(al)} trials one by one: {dt_seq:.3f} s; "
-          f"{agree}/{k * len(al)} records agree with the batched launch", flush=True)
+        print(f"[sequential] system {s} done", flush=True)
+    dt_s = time.perf_counter() - t0
+    res["sequential"] = {"systems": len(systems), "batched_seconds": dt_b, "sequential_seconds": dt_s,
+                         "records_agree": agree, "trials": len(systems) * len(al)}
+    print(f"[sequential] {len(systems) * len(al)} trials one by one: {dt_s:.3f} s against {dt_b:.3f} s batched; "
+          f"{agree}/{len(systems) * len(al)} records agree", flush=True)
     for s in systems:
         s.close()
     if a.out:
