@@ -82,10 +82,13 @@ def load_predictor():
     return pr.load(WEIGHTS)
 
 
-def cpu_baseline(A, b, alpha, omega, sweeps_needed, eps, budget_s=20.0):
+def cpu_baseline(A, b, alpha, omega, sweeps_needed, eps, budget_s=20.0, threads=0):
     """FP64 oracle (plain GADI, the same algorithm) on the host: time a bounded
-    number of outer sweeps and scale per sweep to the sweeps the solve needs."""
+    number of outer sweeps and scale per sweep to the sweeps the solve needs.
+    threads > 0 sets the oracle's OpenMP threads (default: all it is given)."""
     import oracle
+    if threads > 0:
+        oracle.set_num_threads(threads)
     o = oracle.OracleSystem(A)
     k = 1
     t0 = time.perf_counter()
@@ -171,6 +174,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-spmv", action="store_true", help="skip the stand-alone product timing (graph replays)")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="OpenMP threads of the oracle timing (0: all)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with one elementwise copy of 2^26 floats (reads and writes 256 MiB) "
                          "to calibrate hardware byte counters")
@@ -300,7 +304,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         sweeps_needed = fp64["sweeps"] if fp64 else info["outer_sweeps"]
-        cpu = cpu_baseline(A, b, 0.5, 0.5, sweeps_needed, 1e-6)
+        cpu = cpu_baseline(A, b, 0.5, 0.5, sweeps_needed, 1e-6, threads=args.cpu_threads)
         print(f"# cpu oracle: {cpu['seconds_per_sweep']:.3f}s/sweep on {cpu['cores']} threads -> "
               f"{cpu['value']:.1f}s", file=sys.stderr, flush=True)
 

@@ -85,6 +85,13 @@ def _declare(lib):
         lib.oracle_gershgorin.argtypes = [ctypes.c_void_p, f64p]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_num_threads.argtypes = []
+        lib.oracle_set_num_threads.restype = None
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the oracle's OpenMP loops (timing only: the results do not depend on it)."""
+    _lib().oracle_set_num_threads(int(n))
 
 
 def num_threads() -> int:

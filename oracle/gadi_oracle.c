@@ -395,6 +395,15 @@ int oracle_gershgorin(const oracle_sys* s, double* out) {
   return O_OK;
 }
 
+/* Sets the threads of the OpenMP loops (no effect without OpenMP). */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* Threads the OpenMP loops of the oracle use (1 without OpenMP). */
 int oracle_num_threads(void) {
 #ifdef _OPENMP
