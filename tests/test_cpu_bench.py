@@ -1,0 +1,72 @@
+"""Host logic of bench.py (no GPU): the algorithmic byte model behind
+roofline.achieved, the traffic summary's staleness rule, and the one-GPU rule."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+# 3-D 128^3 stencil layout: N rows, 6N - 6 n^2 off-diagonal entries, all in diagonal-style slices
+N = 128 ** 3
+L = {"n": N, "nnz_off": 6 * N - 6 * 128 ** 2, "explicit_entries": 0}
+
+
+def test_linear_in_the_iteration_counts():
+    f = lambda s, h, c, l=1: bench.solve_bytes("fp16", L, s, h, c, l)
+    base = f(0, 0, 0, 0)
+    assert base == 0.0
+    one_res = f(0, 0, 0, 1)
+    per_sweep = f(1, 0, 0, 0)
+    per_cg = f(0, 1, 0, 0)
+    per_cgne = f(0, 0, 1, 0)
+    assert f(10, 20, 30, 2) == pytest.approx(2 * one_res + 10 * per_sweep + 20 * per_cg + 30 * per_cgne)
+    # a launch evaluates one residual more than it corrects: the residual is in every sweep too
+    assert per_sweep > one_res
+
+
+def test_magnitudes_of_one_unit():
+    zo = L["nnz_off"]
+    # residual: double A (values of the off-diagonals and the diagonal), x, b, the scaled output
+    assert bench.solve_bytes("fp16", L, 0, 0, 0, 1) == 8 * (zo + N) + 22 * N
+    # fp16 CG step: the operator once (values + diagonal) and eight half-precision vector accesses
+    assert bench.solve_bytes("fp16", L, 0, 1, 0, 0) == 2 * (zo + N) + 16 * N
+    # a CGNE step applies S twice
+    assert bench.solve_bytes("fp16", L, 0, 0, 1, 0) == 2 * (2 * zo + 8 * N)
+
+
+def test_precision_and_explicit_columns():
+    a = bench.solve_bytes("fp16", L, 5, 50, 20)
+    b = bench.solve_bytes("fp32", L, 5, 50, 20)
+    c = bench.solve_bytes("fp64", L, 5, 50, 20)
+    assert a < b < c
+    L2 = dict(L, explicit_entries=1000)
+    # each product reads a 4-byte column per explicit entry: residual, CG, two per CGNE, the update's S product
+    d = bench.solve_bytes("fp16", L2, 1, 1, 1, 1) - bench.solve_bytes("fp16", L, 1, 1, 1, 1)
+    assert d == 4 * 1000 * (2 + 1 + 2 + 1)
+
+
+def test_stale_traffic_summary_is_ignored(tmp_path, monkeypatch):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.profiled_traffic("w", "fp16")[0] is None
+    f = prof / "solve_kernel_fp16_w_traffic.md"
+    import paper_2501_04229_amd.rocprof_summary as rs
+    good = rs.source_hash(ROOT)
+    monkeypatch.setattr(rs, "source_hash", lambda root: good)
+    f.write_text(f"traffic_bytes_per_launch: 1.5e+10\nsource_sha256: {good}\n")
+    assert bench.profiled_traffic("w", "fp16")[0] == 1.5e10
+    f.write_text("traffic_bytes_per_launch: 1.5e+10\nsource_sha256: 1234\n")
+    assert bench.profiled_traffic("w", "fp16")[0] is None
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr) or "single" in (r.stdout + r.stderr).lower()
