@@ -92,12 +92,14 @@ def test_sampled_rows_of_products(big):
         assert abs(yS[i] - sr) <= (U16 + 10 * U32) * sm + 6e-8, (name, i)
 
 
-def test_fullsize_fp16_solve_properties(big):
-    """FP16-IR from x = 0 to RES <= 1e-10 at (0.5, 0.5) on the device-resident right-hand side."""
+@pytest.mark.parametrize("prec", ["fp16", "fp8"])
+def test_fullsize_fp16_solve_properties(big, prec):
+    """FP16-IR (and the FP8 storage mode) from x = 0 to RES <= 1e-10 at (0.5, 0.5) on the device-resident
+    right-hand side."""
     name, W, g = big
     A, b, xs = W["A"], W["b"], W["xstar"]
     bd = torch.from_numpy(b).cuda()
-    x, info = g.solve(bd, 0.5, 0.5, tol=1e-10, prec="fp16")
+    x, info = g.solve(bd, 0.5, 0.5, tol=1e-10, prec=prec)
     torch.cuda.synchronize()
     assert info["status"] == gadi.OK, info
     xh = x.cpu().numpy()
