@@ -123,3 +123,23 @@ def test_argument_checks():
         g.solve(C, prec="h-d-s")
     with pytest.raises(gadi.GadiError):
         gadi.Sylvester((np.zeros(0), np.zeros(0), np.zeros(0)), A)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "fp64"])
+def test_large_system_properties(prec):
+    """n = 4096 (the timed size): the FP64 residual recomputed by the oracle's products meets the
+    tolerance, and the error against the manufactured X* = 1 obeys the forward bound
+    ||X - X*||_F <= ||R||_F / lambda_min(sym L) with lambda_min(sym L) = 2 lambda_min(sym A) (A = B),
+    the smallest eigenvalue of sym(A) in closed form."""
+    n, r = 4096, 0.1
+    A = gi.paper_tridiag(n, r)
+    Xs, C = gi.sylvester_rhs(A, A, "ones")
+    g = gadi.Sylvester(A, A)
+    X, info = g.solve(torch.from_numpy(C).cuda(), 0.5, 0.5, tol=1e-10, prec=prec, maxit_outer=20000)
+    assert info["status"] == gadi.OK, info
+    Xh = X.cpu().numpy()
+    R = osyl.residual(A, A, C, Xh)
+    assert np.linalg.norm(R) <= 1.0000001e-10 * np.linalg.norm(C)
+    # sym(A) = Tridiag(-1, 2 + 100/(n+1)^2, -1): lambda_min = 2 + 100/(n+1)^2 - 2 cos(pi/(n+1))
+    lmin = 2.0 + 100.0 / (n + 1) ** 2 - 2.0 * np.cos(np.pi / (n + 1))
+    assert np.linalg.norm(Xh - Xs) <= np.linalg.norm(R) / (2.0 * lmin) * 1.0000001
