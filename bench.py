@@ -35,20 +35,22 @@ def solve_bytes(prec: str, L: dict, sweeps: int, inner_h: int, inner_s: int, lau
     Matrix streams follow the packed layout (L = System.layout()): one value per
     structural entry plus an int32 column for entries of explicit slices
     (diagonal-style slices store no column).  Per unit, with N rows, z_o
-    off-diagonal entries, z_e of them in explicit slices, v = value/vector bytes
-    (2 fp16, 4 fp32, 8 fp64), s = inner accumulator bytes (4, or 8 in fp64):
-      residual a1          8 (z_o + N) + 4 z_e + 22 N      (double A, x, b; scaled output)
-      CG step              v (z_o + N) + 4 z_e + 8 v N     (alpha I + H product, 8 vector accesses)
-      CGNE step            2 (v z_o + 4 z_e + 4 v N)       (two S products)
-      update a6            v z_o + 4 z_e + 16 N + 2 s N    (one S product, x read/write)
+    off-diagonal entries, z_e of them in explicit slices, m / d / v = bytes of an
+    off-diagonal value / a diagonal value / a vector entry (fp16 2/2/2, fp32 4/4/4,
+    fp64 8/8/8, fp8 1/2/2: E4M3 values, half diagonal and vectors), s = inner
+    accumulator bytes (4, or 8 in fp64):
+      residual a1          8 (z_o + N) + 4 z_e + 22 N          (double A, x, b; scaled output)
+      CG step              m z_o + d N + 4 z_e + 8 v N         (alpha I + H product, 8 vector accesses)
+      CGNE step            2 (m z_o + 4 z_e + 4 v N)           (two S products)
+      update a6            m z_o + 4 z_e + 16 N + 2 s N        (one S product, x read/write)
     Each launch evaluates one residual more than it applies corrections."""
-    v = {"fp16": 2, "fp32": 4, "fp64": 8}[prec]
+    m, d, v = {"fp16": (2, 2, 2), "fp32": (4, 4, 4), "fp64": (8, 8, 8), "fp8": (1, 2, 2)}[prec]
     sb = 8 if prec == "fp64" else 4
     n, zo, ze = L["n"], L["nnz_off"], L["explicit_entries"]
     res = 8 * (zo + n) + 4 * ze + 22 * n
-    cg = v * (zo + n) + 4 * ze + 8 * v * n
-    cgne = 2 * (v * zo + 4 * ze + 4 * v * n)
-    upd = v * zo + 4 * ze + 16 * n + 2 * sb * n
+    cg = m * zo + d * n + 4 * ze + 8 * v * n
+    cgne = 2 * (m * zo + 4 * ze + 4 * v * n)
+    upd = m * zo + 4 * ze + 16 * n + 2 * sb * n
     return float((sweeps + launches) * res + sweeps * upd + inner_h * cg + inner_s * cgne)
 
 
@@ -168,7 +170,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="convdiff3d_128_beta20")
-    ap.add_argument("--prec", default="fp16", choices=["fp16", "fp32", "fp64"])
+    ap.add_argument("--prec", default="fp16", choices=["fp16", "fp32", "fp64", "fp8"])
     ap.add_argument("--eps-inner", type=float, default=None)
     ap.add_argument("--params", default="mlp", choices=["mlp", "default"])
     ap.add_argument("--no-cpu", action="store_true")
@@ -252,7 +254,7 @@ def main():
                                  inf.get("launches", 1))
     nbytes = tot_bytes / launches
     achieved = tot_bytes / float(np.sum(kernel_s)) / 1e9
-    print(f"# fp16-IR: {step_s:.3f}s/solve, kernel {kern:.3f}s, {achieved:.0f} GB/s algorithmic, "
+    print(f"# {args.prec}-IR: {step_s:.3f}s/solve, kernel {kern:.3f}s, {achieved:.0f} GB/s algorithmic, "
           f"sweeps={info['outer_sweeps']} inner_H={info['inner_H']} inner_S={info['inner_S']} "
           f"relres={info['relres']:.3e} err_vs_x*={rel_err_xstar:.3e} barriers={info['barriers']} "
           f"block0 in barriers {info['barrier_seconds']:.3f}s", file=sys.stderr, flush=True)
@@ -320,7 +322,8 @@ def main():
         "scaling": "strong",
         "vs_baseline": None,
         "dtype": {"fp16": "fp16 storage / fp32 arithmetic inner, f64 residual+update",
-                  "fp32": "f32 inner, f64 residual+update", "fp64": "f64"}[args.prec],
+                  "fp32": "f32 inner, f64 residual+update", "fp64": "f64",
+                  "fp8": "e4m3 values, fp16 vectors / fp32 arithmetic inner, f64 residual+update"}[args.prec],
         "data": "synthetic",
         "layout": lay,
         "config": {"workload": args.workload, "N": n, "nnz": z, "tol": 1e-10,

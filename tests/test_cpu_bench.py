@@ -40,7 +40,10 @@ def test_magnitudes_of_one_unit():
 
 
 def test_precision_and_explicit_columns():
+    e = bench.solve_bytes("fp8", L, 5, 50, 20)
     a = bench.solve_bytes("fp16", L, 5, 50, 20)
+    # E4M3 values save one byte per off-diagonal entry in every inner product (CG, two per CGNE, update)
+    assert a - e == L["nnz_off"] * (50 + 2 * 20 + 5)
     b = bench.solve_bytes("fp32", L, 5, 50, 20)
     c = bench.solve_bytes("fp64", L, 5, 50, 20)
     assert a < b < c
