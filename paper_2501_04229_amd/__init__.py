@@ -7,8 +7,10 @@ fallback: importing fails if the library cannot be loaded.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -110,6 +112,25 @@ def _load():
 
 _lib = _load()
 
+# Handles that still own library memory.  They are destroyed by an exit hook
+# that runs before module teardown and before the HIP runtime's own shutdown,
+# so no device buffer, event or handle outlives the runtime (a profiler that
+# finalises at exit then sees every allocation released).
+_live = weakref.WeakSet()
+
+
+def _track(obj):
+    _live.add(obj)
+
+
+@atexit.register
+def _close_all():
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:  # pragma: no cover - exit path, nothing to report to
+            pass
+
 
 def lib():
     return _lib
@@ -167,6 +188,7 @@ class System:
         self._h = h
         self.meta = A
         self.history = None
+        _track(self)
 
     def close(self):
         # at interpreter exit the module globals may already be gone: nothing to free then
@@ -320,6 +342,7 @@ class Predictor:
         h = ctypes.c_void_p()
         _check(_lib.gadi_mlp_create(int(seed), ctypes.byref(h)), "gadi_mlp_create")
         self._h = h
+        _track(self)
 
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -415,6 +438,7 @@ class Sylvester:
                                     ctypes.byref(h)), "gadi_sylv_setup")
         self._h = h
         self.history = np.zeros(0)
+        _track(self)
 
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:

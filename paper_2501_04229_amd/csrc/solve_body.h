@@ -337,7 +337,9 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
   const AT two_m_omega = (AT)(2.0 - a.omega);
   const double eps_h2 = a.eps_h * a.eps_h;
   const double eps_s2 = a.eps_s * a.eps_s;
-  const int overflow_status = Mode::id == GADI_PREC_FP16_IR ? GADI_EOVERFLOW16 : GADI_EDIVERGED;
+  // a non-finite inner quantity is a half-precision overflow in every mode that
+  // stores its Krylov vectors in half (fp16, h-d-s, h-s-s, fp8)
+  const int overflow_status = std::is_same<VT, __half>::value ? GADI_EOVERFLOW16 : GADI_EDIVERGED;
 
   // value rounded to the storage type and read back
   auto rnd = [](AT v) { return ld<AT>(st<VT>(v)); };

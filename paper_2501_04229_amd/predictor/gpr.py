@@ -10,7 +10,7 @@ import ctypes
 
 import numpy as np
 
-from .. import _check, lib
+from .. import _check, _track, lib
 
 
 def _dp(a):
@@ -28,6 +28,7 @@ class GPR:
         h = ctypes.c_void_p()
         _check(lib().gadi_gpr_fit(_dp(self._x), _dp(self._y), len(self._x), ctypes.byref(h)), "gadi_gpr_fit")
         self._h = h
+        _track(self)
 
     def close(self):
         if getattr(self, "_h", None) and lib() is not None:

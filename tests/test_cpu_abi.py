@@ -73,3 +73,15 @@ def test_one_hip_runtime_when_the_package_is_imported_first():
     out = subprocess.run([os.sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr[-2000:]
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_live_handles_are_closed_by_the_exit_hook():
+    """Every handle that owns library memory is registered, and the exit hook closes it
+    (host-only GPR handle: no device needed)."""
+    import numpy as np
+    import paper_2501_04229_amd as gadi
+    from paper_2501_04229_amd.predictor.gpr import GPR
+    g = GPR(np.array([1.0, 2.0, 3.0, 4.0]), np.array([0.5, 0.1, -0.2, -0.6]))
+    assert g in gadi._live and g._h
+    gadi._close_all()
+    assert g._h is None

@@ -311,16 +311,18 @@ def test_fp16_regularisation_grid(alpha, omega):
     assert np.linalg.norm(b - o.spmv("A", x)) <= 1.0000001e-10 * np.linalg.norm(b)
 
 
-def test_fp16_small_alpha_fails_cleanly_where_fp32_continues():
+@pytest.mark.parametrize("prec", ["fp16", "h-d-s", "h-s-s", "fp8"])
+def test_fp16_small_alpha_fails_cleanly_where_fp32_continues(prec):
     """Too little regularisation: with alpha = 1e-3 the normal operator I - S^2/alpha^2 of the
-    S-step exceeds the half range (||S||/alpha ~ 3.5e3 here); the half-precision solve stops with
-    EOVERFLOW16 and a finite iterate, while single precision keeps reducing the residual (cf. the
-    paper's Table 3d, where half-precision inner solves fail at the smallest alpha)."""
+    S-step exceeds the half range (||S||/alpha ~ 3.5e3 here); every mode that stores its Krylov
+    vectors in half (fp16, h-d-s, h-s-s, fp8) stops with EOVERFLOW16 and a finite iterate, while
+    single precision keeps reducing the residual (cf. the paper's Table 3d, where half-precision
+    inner solves fail at the smallest alpha)."""
     A = gi.convdiff(16, 3, 20.0)
     g = gadi.System(A)
     o = oracle.OracleSystem(A)
     xs, b = gi.rhs_for(A, "uniform", 1)
-    x, info = g.solve(b, 1e-3, 0.5, tol=1e-10, prec="fp16", maxit_outer=5)
+    x, info = g.solve(b, 1e-3, 0.5, tol=1e-10, prec=prec, maxit_outer=5)
     assert info["status"] == gadi.EOVERFLOW16, info
     assert np.all(np.isfinite(x))
     x, info = g.solve(b, 1e-3, 0.5, tol=1e-10, prec="fp32", maxit_outer=5, maxit_inner=500)

@@ -73,3 +73,18 @@ def test_standardise_guards_zero_variance():
     F = np.array([[1.0, 0.0, 5.0], [3.0, 0.0, 5.0]])
     mu, sd = mlp.standardise_fit(F)
     assert np.array_equal(mu, [2.0, 0.0, 5.0]) and np.array_equal(sd, [1.0, 1.0, 1.0])
+
+
+def test_adam_second_step_worked_value():
+    """Two Adam steps on one parameter, gradients +1 then -2, lr = 0.1, worked by hand:
+    step 1: m = 0.1, v = 0.001, bias-corrected 1 and 1, theta moves by -0.1;
+    step 2: m = 0.9 * 0.1 - 0.2 = -0.11, v = 0.999 * 0.001 + 0.004 = 0.004999,
+    m^ = -0.11 / 0.19 = -0.5789473684..., v^ = 0.004999 / 0.001999 = 2.5007503751...,
+    theta moves by -0.1 m^ / sqrt(v^) = +0.0366103527035845565...
+    A bias correction with the wrong power of beta, or a moment not carried over, fails."""
+    th0 = np.array([0.25])
+    th1, m, v = mlp.adam_step(th0, np.array([1.0]), np.zeros(1), np.zeros(1), 1, lr=0.1, eps=0.0)
+    assert abs(th1[0] - 0.15) <= 1e-15
+    th2, m, v = mlp.adam_step(th1, np.array([-2.0]), m, v, 2, lr=0.1, eps=0.0)
+    assert abs(m[0] + 0.11) <= 1e-15 and abs(v[0] - 0.004999) <= 1e-17
+    assert abs(th2[0] - (0.15 + 0.0366103527035845565282265)) <= 1e-15

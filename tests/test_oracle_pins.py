@@ -349,3 +349,32 @@ def test_pins_catch_planted_oracle_mistakes(plant):
     bad = oracle.OracleSystem(A, plant=plant)
     r = bad.gadi(b, 0.5, 0.5, tol=0.0, eps_h=1e-14, eps_s=1e-14, maxit_out=2, maxit_in=10 * A.n)
     assert np.linalg.norm(r["x"] - co[2]) > 1e-3 * np.linalg.norm(co[2])
+
+
+@pytest.mark.parametrize("n,dim,beta", [(5, 2, (10.0, 3.0)), (4, 3, (20.0, 1.0, 7.0)), (6, 2, 0.5),
+                                        (3, 3, 100.0)])
+def test_features_against_the_dense_matrix(n, dim, beta):
+    """Every predictor feature against the assembled matrix itself (no closed form reused):
+    lambda_min(H) from eigvalsh of the dense (A + A^T)/2, the cell Peclet number max_a beta_a h / 2
+    as the largest |entry| of the dense (A - A^T)/2 (the skew entries are +-r_a), and the
+    Gershgorin quantities from dense row sums.  A wrong mesh width (h = 1/n), a wrong factor in
+    the Peclet number or a wrong eigenvalue formula fails."""
+    A = gi.convdiff(n, dim, beta)
+    D = np.zeros((A.n, A.n))
+    for i in range(A.n):
+        for k in range(A.row_ptr[i], A.row_ptr[i + 1]):
+            D[i, A.col[k]] += A.val[k]
+    H = 0.5 * (D + D.T)
+    S = 0.5 * (D - D.T)
+    f = oracle.features(A)
+    b = np.broadcast_to(np.asarray(beta, dtype=float), (dim,))
+    assert f[0] == pytest.approx(np.log(n ** dim), abs=1e-14)
+    assert f[1] == dim
+    assert f[2] == pytest.approx(np.log10(b.mean()), abs=1e-14)
+    assert 10 ** f[3] == pytest.approx(np.abs(S).max(), rel=1e-12)
+    assert 10 ** f[4] == pytest.approx(np.linalg.eigvalsh(H)[0], rel=1e-9)
+    off_h = np.abs(H - np.diag(np.diag(H))).sum(axis=1)
+    assert 10 ** f[5] == pytest.approx((np.diag(H) + off_h).max(), rel=1e-12)
+    rs = np.abs(S).sum(axis=1)
+    assert 10 ** f[6] == pytest.approx(rs.max(), rel=1e-12)
+    assert 10 ** f[7] == pytest.approx(rs.min(), rel=1e-12)
