@@ -1,14 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark: time-to-1e-10 of FP16-IR GADI vs plain FP64 GADI on one MI355X.
 
-One step = one complete GADI-IR solve (every hot-path phase: FP64 residual,
-CG on alpha I + H, CGNE on alpha I + S, FP64 update, repeated to RES <= 1e-10)
-of the 3-D convection-diffusion system, 128^3 grid, beta = (20, 20, 20),
-b = A x* with x* ~ U(-1, 1) seed 0, inputs resident in device memory.
+One step = one complete GADI-IR solve with the MLP-predicted (alpha, omega)
+(features, prediction, the guarded first run and its continuation; every
+hot-path phase: FP64 residual, CG on alpha I + H, CGNE on alpha I + S, FP64
+update, repeated to RES <= 1e-10) of the 3-D convection-diffusion system of
+Section 4.1 on a 256^3 grid, beta ~ U(0, 100) per axis (seed 1), b = A 1,
+inputs resident in device memory.  The 128^3 system (beta = 20, x* ~ U(-1, 1)
+seed 0), whose working set fits the 256 MB Infinity Cache, is measured as a
+sub-record.
 
-Prints one JSON line.  The plain FP64 GADI solve (inner CG/CGNE to 1e-6) is
-timed on the same GPU for the comparison; the FP64 CPU oracle is timed on a
-bounded sample of outer sweeps on the host cores (cpu_baseline leg).
+Prints one JSON line.  Also measured: the same solve at the outer tolerance
+that makes a relative 1e-8 match with the oracle's solution provable; plain
+FP64 GADI on the same GPU at the same inner tolerance (the headline ratio) and
+at inner 1e-6; the stand-alone products; and the FP64 CPU oracle on a bounded
+sample of outer sweeps on the host cores, with all threads and with one
+(cpu_baseline leg).
 """
 from __future__ import annotations
 
@@ -164,18 +171,155 @@ def spmv_gbs(g, A, alpha, reps=50):
             "fp64_A_GBs": by64 / dt64 / 1e9, "timing": "graph of %d products, best of 3 replays" % reps}
 
 
+def survey_bytes(prec: str, z: int, zs: int, n: int, sweeps: int, inner_h: int, inner_s: int,
+                 launches: int = 1) -> float:
+    """Algorithmic bytes of the method in CSR terms, per unit (z = nnz of A with
+    its diagonal, z_s = nnz of S, N rows; v = bytes of a stored value and of a
+    vector entry, 2 in fp16, 1 for an E4M3 value, 4 in fp32, 8 in fp64), with a
+    4-byte column index per entry as a CSR product moves it:
+      residual a1   12 z + 22 N                   (double values, index, x, b, scaled output)
+      CG step       (v + 4) z + 8 v N              (one product, 8 vector accesses)
+      CGNE step     2 ((v + 4) z_s + 4 v N)        (two S products)
+      update a6     18 N                           (x read and written, the half update read)
+    The fp16 figures are 12 z + 22 N, 6 z + 16 N, 2 (6 z_s + 8 N) and 18 N.  The
+    packed diagonal layout stores no column index, so the bytes the kernel moves
+    (solve_bytes) are fewer."""
+    mv = {"fp16": (2, 2), "fp32": (4, 4), "fp64": (8, 8), "fp8": (1, 2)}[prec]
+    m, v = mv
+    res = 12 * z + 22 * n
+    cg = (m + 4) * z + 8 * v * n
+    cgne = 2 * ((m + 4) * zs + 4 * v * n)
+    upd = 18 * n if prec != "fp64" else 24 * n
+    return float((sweeps + launches) * res + sweeps * upd + inner_h * cg + inner_s * cgne)
+
+
+def lambda_min_H(A) -> float:
+    """Smallest eigenvalue of the symmetric part of the Section 4.1 matrix:
+    dim (2 - 2 cos(pi h)), h = 1 / (n + 1) (the h^2-scaled Laplacian)."""
+    return A.dim * (2.0 - 2.0 * math.cos(math.pi / (A.grid + 1)))
+
+
+def parity_tolerance(A, b, xstar, target=1e-8, ref_tol=1e-13) -> float:
+    """Outer tolerance at which a relative `target` match with the oracle's
+    solution (run to RES ref_tol) is provable: ||x - x_ref|| <= (||r|| +
+    ||r_ref||) / sigma_min(A) and sigma_min(A) >= lambda_min(H) for a positive
+    real A; the manufactured x* stands in for ||x_ref||."""
+    t = target * lambda_min_H(A) * float(np.linalg.norm(xstar)) / float(np.linalg.norm(b)) - ref_tol
+    return min(1e-10, 0.9 * t)
+
+
+def host_cpu():
+    """(CPUs this process may run on, CPU model name)."""
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        ncpu = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:  # pragma: no cover
+        pass
+    return ncpu, model
+
+
+def solve_step(g, A, bd, pred, prec, eps, tol=1e-10):
+    """One step: with the predictor, solve_auto (prediction judged by the default);
+    without, a plain solve at (0.5, 0.5).  Returns (x, info, launches, used)."""
+    from paper_2501_04229_amd import predictor as pr
+    if pred is not None:
+        x, info, used = pr.solve_auto(g, A, bd, pred, tol=tol, prec=prec, eps_inner=eps)
+        return x, info, info["launches"], used
+    x, info = g.solve(bd, 0.5, 0.5, tol=tol, prec=prec, eps_inner=eps)
+    info["launches"] = 1
+    return x, info, 1, "default"
+
+
+def timed_solves(g, A, bd, pred, prec, eps, steps, tol=1e-10):
+    """`steps` solves between two device synchronisations; returns (wall seconds
+    per solve, infos, last x)."""
+    import torch
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x = None
+    for _ in range(steps):
+        x, info, _, used = solve_step(g, A, bd, pred, prec, eps, tol)
+        info["used"] = used
+        infos.append(info)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, infos, x
+
+
+def summarize(infos, prec, lay, A):
+    """Kernel seconds, launches and both byte models over a list of solve records."""
+    zs = A.nnz - A.n
+    kern = float(sum(i["seconds"] for i in infos))
+    launches = int(sum(i.get("launches", 1) for i in infos))
+    moved = sum(solve_bytes(prec, lay, i["outer_sweeps"], i["inner_H"], i["inner_S"], i.get("launches", 1))
+                for i in infos)
+    alg = sum(survey_bytes(prec, A.nnz, zs, A.n, i["outer_sweeps"], i["inner_H"], i["inner_S"],
+                           i.get("launches", 1)) for i in infos)
+    return {"kernel_seconds": kern, "launches": launches, "moved_bytes": moved, "algorithmic_bytes": alg}
+
+
+def log(msg):
+    print("# " + msg, file=sys.stderr, flush=True)
+
+
+def measure_sub(workload, args, pred):
+    """The cache-resident 128^3 sub-record: the FP16-IR+MLP solve and the default."""
+    import torch
+    import gadi_inputs as gi
+    import paper_2501_04229_amd as gadi
+    W = gi.workload(workload)
+    A, b, xs = W["A"], W["b"], W["xstar"]
+    g = gadi.System(A)
+    bd = torch.from_numpy(b).cuda()
+    eps = args.eps_inner
+    for _ in range(max(1, args.warmup)):
+        solve_step(g, A, bd, pred, args.prec, eps)
+    step_s, infos, x = timed_solves(g, A, bd, pred, args.prec, eps, args.steps)
+    sm = summarize(infos, args.prec, g.layout(), A)
+    info = infos[-1]
+    tp = parity_tolerance(A, b, xs)
+    tps, pinf, xp = timed_solves(g, A, bd, pred, args.prec, eps, 2, tol=tp)
+    _, idf = g.solve(bd, 0.5, 0.5, tol=1e-10, prec=args.prec, eps_inner=eps)
+    out = {"workload": workload, "N": A.n, "nnz": A.nnz, "seconds_per_solve": step_s,
+           "status": info["status_str"], "used": info["used"], "sweeps": info["outer_sweeps"],
+           "inner_H": info["inner_H"], "inner_S": info["inner_S"], "relres": info["relres"],
+           "rel_err_vs_xstar": float(np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs)),
+           "parity_tol": tp, "seconds_at_parity_tol": tps,
+           "rel_err_vs_xstar_at_parity_tol": float(np.linalg.norm(xp.cpu().numpy() - xs) / np.linalg.norm(xs)),
+           "default_params_seconds": idf["seconds"], "default_params_sweeps": idf["outer_sweeps"],
+           "algorithmic_GBs": sm["algorithmic_bytes"] / sm["kernel_seconds"] / 1e9,
+           "moved_GBs": sm["moved_bytes"] / sm["kernel_seconds"] / 1e9,
+           "note": "working set within the 256 MB Infinity Cache: effective rates, no HBM roofline claim"}
+    log(f"sub-record {workload}: {step_s:.4f}s/solve ({info['outer_sweeps']} sweeps, used {info['used']}), "
+        f"at parity tol {tp:.2e}: {tps:.4f}s; default {idf['seconds']:.4f}s")
+    g.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="convdiff3d_128_beta20")
+    ap.add_argument("--workload", default="convdiff3d_256_betaU100")
+    ap.add_argument("--sub-workload", default="convdiff3d_128_beta20",
+                    help="second, cache-resident workload reported as a sub-record ('' to skip)")
     ap.add_argument("--prec", default="fp16", choices=["fp16", "fp32", "fp64", "fp8"])
     ap.add_argument("--eps-inner", type=float, default=None)
     ap.add_argument("--params", default="mlp", choices=["mlp", "default"])
+    ap.add_argument("--fp64-steps", type=int, default=3, help="timed plain FP64 GADI solves per inner tolerance")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-spmv", action="store_true", help="skip the stand-alone product timing (graph replays)")
+    ap.add_argument("--no-parity-tol", action="store_true", help="skip the solves at the parity tolerance")
     ap.add_argument("--cpu-threads", type=int, default=0, help="OpenMP threads of the oracle timing (0: all)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with one elementwise copy of 2^26 floats (reads and writes 256 MiB) "
@@ -197,119 +341,110 @@ def main():
     A, b, xs = W["A"], W["b"], W["xstar"]
     g = gadi.System(A)
     setup_s = time.perf_counter() - t_setup
-    z = A.nnz
-    zs = A.nnz - A.n
-    n = A.n
+    n, z = A.n, A.nnz
     bd = torch.from_numpy(b).cuda()
     eps = args.eps_inner
+    eps_used = eps if eps is not None else gadi.options(args.prec).eps_inner
     pred = load_predictor() if args.params == "mlp" else None
     from paper_2501_04229_amd import predictor as pr
     alpha, omega, psrc = 0.5, 0.5, "default"
     if pred is not None:
         alpha, omega = pr.predict(pred, g, A)
         psrc = "mlp"
-
-    def run(prec, al, om, e):
-        """One step: with the predictor, solve_auto (prediction guarded by the default);
-        without, a plain solve.  Returns (x, info, launches, used)."""
-        if pred is not None and prec == args.prec:
-            x, info, used = pr.solve_auto(g, A, bd, pred, tol=1e-10, prec=prec, eps_inner=e)
-            return x, info, info["launches"], used
-        x, info = g.solve(bd, al, om, tol=1e-10, prec=prec, eps_inner=e)
-        return x, info, 1, "fixed"
-
-    print(f"# workload {args.workload}: N={n} nnz={z} setup {setup_s:.1f}s params {psrc} "
-          f"alpha={alpha:.4g} omega={omega:.4g}", file=sys.stderr, flush=True)
+    log(f"workload {args.workload}: N={n} nnz={z} setup {setup_s:.1f}s params {psrc} "
+        f"alpha={alpha:.4g} omega={omega:.4g}")
     for _ in range(args.warmup):
-        x, info, nl, used = run(args.prec, alpha, omega, eps)
-        print(f"# warmup: {info['status_str']} used={used} sweeps={info['outer_sweeps']} inner_H={info['inner_H']} "
-              f"inner_S={info['inner_S']} {info['seconds']:.3f}s", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    kernel_s = []
-    infos = []
-    launches = 0
-    for _ in range(args.steps):
-        x, info, nl, used = run(args.prec, alpha, omega, eps)
-        kernel_s.append(info["seconds"])
-        infos.append(info)
-        launches += nl
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    step_s = (t1 - t0) / args.steps
+        x, info, nl, used = solve_step(g, A, bd, pred, args.prec, eps)
+        log(f"warmup: {info['status_str']} used={used} sweeps={info['outer_sweeps']} inner_H={info['inner_H']} "
+            f"inner_S={info['inner_S']} {info['seconds']:.3f}s")
+    step_s, infos, x = timed_solves(g, A, bd, pred, args.prec, eps, args.steps)
     info = infos[-1]
+    used = info["used"]
     if info["status"] != gadi.OK:
-        print(f"# solve did not converge: {info}", file=sys.stderr, flush=True)
+        log(f"solve did not converge: {info}")
     prof = g.phase_profile()
-    print("# phase profile (block 0 compute s, count): " +
-          ", ".join(f"{k} {v[0]:.4f}/{v[1]}" for k, v in prof.items() if v[1]), file=sys.stderr, flush=True)
+    log("phase profile (block 0 compute s, count): " +
+        ", ".join(f"{k} {v[0]:.4f}/{v[1]}" for k, v in prof.items() if v[1]))
     xh = x.cpu().numpy()
     rel_err_xstar = float(np.linalg.norm(xh - xs) / np.linalg.norm(xs))
-    kern = float(np.mean(kernel_s))
-    # every solve-kernel launch of the timed region: total algorithmic bytes / total device time
     lay = g.layout()
-    tot_bytes = 0.0
-    for inf in infos:
-        tot_bytes += solve_bytes(args.prec, lay, inf["outer_sweeps"], inf["inner_H"], inf["inner_S"],
-                                 inf.get("launches", 1))
-    nbytes = tot_bytes / launches
-    achieved = tot_bytes / float(np.sum(kernel_s)) / 1e9
-    print(f"# {args.prec}-IR: {step_s:.3f}s/solve, kernel {kern:.3f}s, {achieved:.0f} GB/s algorithmic, "
-          f"sweeps={info['outer_sweeps']} inner_H={info['inner_H']} inner_S={info['inner_S']} "
-          f"relres={info['relres']:.3e} err_vs_x*={rel_err_xstar:.3e} barriers={info['barriers']} "
-          f"block0 in barriers {info['barrier_seconds']:.3f}s", file=sys.stderr, flush=True)
+    sm = summarize(infos, args.prec, lay, A)
+    launches = sm["launches"]
+    launch_s = sm["kernel_seconds"] / launches
+    achieved = sm["algorithmic_bytes"] / sm["kernel_seconds"] / 1e9
+    moved = sm["moved_bytes"] / sm["kernel_seconds"] / 1e9
+    nb, thr = g.solver_blocks()
+    log(f"{args.prec}-IR: {step_s:.4f}s/solve, kernel {sm['kernel_seconds'] / args.steps:.4f}s, "
+        f"{achieved:.0f} GB/s algorithmic, {moved:.0f} GB/s moved, sweeps={info['outer_sweeps']} "
+        f"inner_H={info['inner_H']} inner_S={info['inner_S']} relres={info['relres']:.3e} "
+        f"err_vs_x*={rel_err_xstar:.3e} barriers={info['barriers']} "
+        f"block0 in barriers {info['barrier_seconds']:.3f}s, launch {nb} x {thr}")
+
+    # the outer tolerance that makes the 1e-8 match with the oracle provable
+    par = None
+    if not args.no_parity_tol:
+        tp = parity_tolerance(A, b, xs)
+        tps, pinf, xp = timed_solves(g, A, bd, pred, args.prec, eps, min(args.steps, 3), tol=tp)
+        ip = pinf[-1]
+        par = {"parity_tol": tp, "seconds_per_solve": tps, "status": ip["status_str"],
+               "sweeps": ip["outer_sweeps"], "relres": ip["relres"],
+               "rel_err_vs_xstar": float(np.linalg.norm(xp.cpu().numpy() - xs) / np.linalg.norm(xs))}
+        log(f"at the parity tolerance {tp:.3e}: {tps:.4f}s/solve, sweeps={ip['outer_sweeps']}, "
+            f"err_vs_x*={par['rel_err_vs_xstar']:.3e}")
 
     # the same precision with the default parameters, no predictor (reference)
     xdf, idf = g.solve(bd, 0.5, 0.5, tol=1e-10, prec=args.prec, eps_inner=eps)
     torch.cuda.synchronize()
-    fp16_default = {"seconds": idf["seconds"], "status": idf["status_str"], "sweeps": idf["outer_sweeps"],
+    default_same = {"seconds": idf["seconds"], "status": idf["status_str"], "sweeps": idf["outer_sweeps"],
                     "inner_H": idf["inner_H"], "inner_S": idf["inner_S"], "relres": idf["relres"]}
-    print(f"# {args.prec} default (0.5, 0.5): {idf['seconds']:.3f}s sweeps={idf['outer_sweeps']}",
-          file=sys.stderr, flush=True)
+    log(f"{args.prec} default (0.5, 0.5): {idf['seconds']:.3f}s sweeps={idf['outer_sweeps']}")
 
     fp64 = None
     if not args.no_fp64:
-        run("fp64", 0.5, 0.5, 1e-6)  # first call tunes the FP64 launch shape
-        torch.cuda.synchronize()
-        tf0 = time.perf_counter()
-        x64, i64, _, _ = run("fp64", 0.5, 0.5, 1e-6)
-        torch.cuda.synchronize()
-        wall64 = time.perf_counter() - tf0
-        x64h = x64.cpu().numpy()
-        nb64 = solve_bytes("fp64", lay, i64["outer_sweeps"], i64["inner_H"], i64["inner_S"])
-        fp64 = {"seconds": i64["seconds"], "wall_seconds": wall64, "status": i64["status_str"],
-                "sweeps": i64["outer_sweeps"],
-                "inner_H": i64["inner_H"], "inner_S": i64["inner_S"], "relres": i64["relres"],
-                "rel_err_vs_xstar": float(np.linalg.norm(x64h - xs) / np.linalg.norm(xs)),
-                "algorithmic_GBs": nb64 / i64["seconds"] / 1e9,
-                "rel_diff_vs_fp16ir": float(np.linalg.norm(xh - x64h) / np.linalg.norm(x64h))}
-        print(f"# fp64 GADI: {i64['seconds']:.3f}s sweeps={i64['outer_sweeps']} inner_H={i64['inner_H']} "
-              f"inner_S={i64['inner_S']} relres={i64['relres']:.3e}", file=sys.stderr, flush=True)
-        # the same plain FP64 GADI with the reduced-precision solve's inner tolerance: separates the
-        # effect of the precision from that of the inner tolerance (informational)
-        eps_rp = gadi.options(args.prec).eps_inner
-        torch.cuda.synchronize()
-        tf0 = time.perf_counter()
-        _, i64e, _, _ = run("fp64", 0.5, 0.5, eps_rp)
-        torch.cuda.synchronize()
-        fp64["same_inner_eps"] = {"eps_inner": eps_rp, "seconds": i64e["seconds"],
-                                  "wall_seconds": time.perf_counter() - tf0, "status": i64e["status_str"],
-                                  "sweeps": i64e["outer_sweeps"], "inner_H": i64e["inner_H"],
-                                  "inner_S": i64e["inner_S"]}
-        print(f"# fp64 GADI, inner {eps_rp:g}: {i64e['seconds']:.3f}s sweeps={i64e['outer_sweeps']}",
-              file=sys.stderr, flush=True)
+        fp64 = {}
+        # plain FP64 GADI at the reduced-precision solve's inner tolerance first (the precision alone),
+        # then at the 1e-6 inner tolerance of the baseline configuration
+        for key, e64 in (("same_inner_eps", eps_used), ("inner_1e-6", 1e-6)):
+            solve_step(g, A, bd, None, "fp64", e64)  # the first call also tunes the FP64 launch shape
+            w64, i64s, x64 = timed_solves(g, A, bd, None, "fp64", e64, args.fp64_steps)
+            i64 = i64s[-1]
+            s64 = summarize(i64s, "fp64", lay, A)
+            fp64[key] = {"eps_inner": e64, "wall_seconds": w64, "kernel_seconds": s64["kernel_seconds"] / len(i64s),
+                         "solves_timed": len(i64s), "status": i64["status_str"], "sweeps": i64["outer_sweeps"],
+                         "inner_H": i64["inner_H"], "inner_S": i64["inner_S"], "relres": i64["relres"],
+                         "rel_err_vs_xstar": float(np.linalg.norm(x64.cpu().numpy() - xs) / np.linalg.norm(xs)),
+                         "algorithmic_GBs": s64["algorithmic_bytes"] / s64["kernel_seconds"] / 1e9}
+            log(f"fp64 GADI, inner {e64:g}: {w64:.3f}s/solve sweeps={i64['outer_sweeps']} "
+                f"inner_H={i64['inner_H']} inner_S={i64['inner_S']}")
     sp = None
     if not args.no_spmv:
         sp = spmv_gbs(g, A, alpha)
-        print(f"# spmv: {sp}", file=sys.stderr, flush=True)
+        log(f"spmv: {sp}")
 
     cpu = None
     if not args.no_cpu:
-        sweeps_needed = fp64["sweeps"] if fp64 else info["outer_sweeps"]
+        sweeps_needed = fp64["inner_1e-6"]["sweeps"] if fp64 else info["outer_sweeps"]
+        ncpu, model = host_cpu()
         cpu = cpu_baseline(A, b, 0.5, 0.5, sweeps_needed, 1e-6, threads=args.cpu_threads)
-        print(f"# cpu oracle: {cpu['seconds_per_sweep']:.3f}s/sweep on {cpu['cores']} threads -> "
-              f"{cpu['value']:.1f}s", file=sys.stderr, flush=True)
+        nthr = cpu["cores"]
+        one = cpu_baseline(A, b, 0.5, 0.5, sweeps_needed, 1e-6, budget_s=8.0, threads=1)
+        import oracle
+        oracle.set_num_threads(nthr)
+        cpu["affinity_cpus"] = ncpu
+        cpu["cpu_model"] = model
+        cpu["one_thread"] = {k: one[k] for k in ("value", "seconds_per_sweep", "sample_sweeps", "cores")}
+        cpu["extrapolated"] = True
+        log(f"cpu oracle: {cpu['seconds_per_sweep']:.3f}s/sweep on {cpu['cores']} threads -> "
+            f"{cpu['value']:.1f}s; 1 thread {one['seconds_per_sweep']:.3f}s/sweep -> {one['value']:.1f}s ({model})")
+    g.close()
+    sub = None
+    if args.sub_workload:
+        sub = measure_sub(args.sub_workload, args, pred)
 
+    speed = None
+    if fp64:
+        speed = {"same_inner_eps": fp64["same_inner_eps"]["wall_seconds"] / step_s,
+                 "inner_1e-6": fp64["inner_1e-6"]["wall_seconds"] / step_s}
     out = {
         "metric": METRIC,
         "value": step_s,
@@ -321,36 +456,40 @@ def main():
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": {"fp16": "fp16 storage / fp32 arithmetic inner, f64 residual+update",
+        "dtype": {"fp16": "f16 storage / f32 arithmetic inner, f64 residual+update",
                   "fp32": "f32 inner, f64 residual+update", "fp64": "f64",
-                  "fp8": "e4m3 values, fp16 vectors / fp32 arithmetic inner, f64 residual+update"}[args.prec],
+                  "fp8": "e4m3 values, f16 vectors / f32 arithmetic inner, f64 residual+update"}[args.prec],
         "data": "synthetic",
-        "layout": lay,
-        "config": {"workload": args.workload, "N": n, "nnz": z, "tol": 1e-10,
-                   "eps_inner": eps if eps is not None else gadi.options(args.prec).eps_inner,
+        "config": {"workload": args.workload, "N": n, "nnz": z, "tol": 1e-10, "eps_inner": eps_used,
                    "alpha_predicted": alpha, "omega_predicted": omega, "params": psrc, "used": used,
-                   "prec": args.prec,
-                   "solve_launch_blocks_threads": list(g.solver_blocks())},
+                   "prec": args.prec, "solve_launch_blocks_threads": [nb, thr],
+                   "tiles_per_block": lay["npad"] / thr / nb},
+        "layout": lay,
         "solve": {"status": info["status_str"], "sweeps": info["outer_sweeps"], "inner_H": info["inner_H"],
                   "inner_S": info["inner_S"], "relres": info["relres"], "rel_err_vs_xstar": rel_err_xstar,
-                  "kernel_seconds": kern, "barriers": info["barriers"],
+                  "kernel_seconds_per_solve": sm["kernel_seconds"] / args.steps, "barriers": info["barriers"],
                   "barrier_seconds_block0": info["barrier_seconds"]},
-        "default_params_same_prec": fp16_default,
+        "at_parity_tol": par,
+        "default_params_same_prec": default_same,
         "fp64_gadi": fp64,
-        "speedup_vs_fp64_gadi": (fp64["wall_seconds"] / step_s) if fp64 else None,
+        "speedup_vs_fp64_gadi": speed,
         "spmv": sp,
         "phase_profile_last_launch": {k: {"seconds": v[0], "count": v[1]} for k, v in prof.items() if v[1]},
         "roofline": {"bound": "hbm", "kernel": f"solve_kernel<{args.prec}>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "algorithmic_bytes_per_launch": nbytes, "launches": launches,
-                     "launch_seconds_mean": float(np.sum(kernel_s)) / launches, "traffic": None},
+                     "algorithmic_bytes_per_launch": sm["algorithmic_bytes"] / launches,
+                     "byte_model": "CSR per-unit figures (survey_bytes)",
+                     "moved_GBs": moved, "moved_frac": moved / HBM_PEAK_GBS,
+                     "moved_bytes_per_launch": sm["moved_bytes"] / launches,
+                     "launches": launches, "launch_seconds_mean": launch_s, "traffic": None},
         "cpu_baseline": cpu,
+        "sub_record": sub,
     }
     traffic, tsrc = profiled_traffic(args.workload, args.prec)
     out["roofline"]["traffic"] = traffic
     out["roofline"]["traffic_source"] = tsrc
     if traffic:
-        out["roofline"]["traffic_over_algorithmic"] = traffic / nbytes
+        out["roofline"]["traffic_over_moved"] = traffic / (sm["moved_bytes"] / launches)
     if args.copy_calibration:
         xc = torch.ones(1 << 26, device="cuda", dtype=torch.float32)
         yc = torch.empty_like(xc)

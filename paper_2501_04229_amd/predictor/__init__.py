@@ -21,10 +21,10 @@ parameter of the symmetric part alone), so the network learns a scale-free
 correction and the size dependence of alpha comes from the closed-form
 spectrum; libgadi applies alpha = alpha_ref 10^y0 at prediction time.
 
-The default parameters (0.5, 0.5) are the fallback: `solve_auto` runs the
-prediction for a few sweeps and replaces it by the default only if that run
-fails or its measured contraction rate cannot reach the tolerance within the
-sweep budget.
+The default parameters (0.5, 0.5) are both the fallback and the judge:
+`solve_auto` runs the prediction for a few sweeps and replaces it by the
+default if that run fails, or if at its measured contraction rate it would
+need more work to reach the tolerance than the default would.
 """
 from __future__ import annotations
 
@@ -174,62 +174,102 @@ def predict(p, system, A):
     return p.predict(f)
 
 
-def _projected_sweeps(hist, tol):
-    """Sweeps still needed to reach RES <= tol, from the contraction rate fitted
-    (least squares on log RES) over the last third of a probe's history (the
-    early sweeps contract fast modes and overstate the rate)."""
+def _log_rate(hist):
+    """Fitted log contraction per sweep (least squares on log RES) over the last
+    third of a run's history (the early sweeps contract fast modes and overstate
+    the rate), or None when the run is too short or not contracting."""
     h = np.asarray(hist, dtype=np.float64)
     h = h[np.isfinite(h) & (h > 0)]
     if len(h) < 6:
-        return math.inf
+        return None
     k0 = (2 * len(h)) // 3
-    k = np.arange(len(h))[k0:]
-    y = np.log(h[k0:])
-    slope = np.polyfit(k, y, 1)[0]
-    if not slope < 0:
+    slope = float(np.polyfit(np.arange(len(h))[k0:], np.log(h[k0:]), 1)[0])
+    return slope if slope < 0 else None
+
+
+def _projected_sweeps(hist, tol):
+    """Sweeps still needed to reach RES <= tol at the fitted contraction rate."""
+    slope = _log_rate(hist)
+    h = np.asarray(hist, dtype=np.float64)
+    if slope is None or not len(h) or not (h[-1] > 0):
         return math.inf
     return max(0.0, (math.log(tol) - math.log(h[-1])) / slope)
+
+
+def default_cost(system, b, probe=32, **kw):
+    """(log contraction per sweep, work per sweep) of the default parameters on
+    this system, measured once per handle, precision and inner tolerance by a
+    `probe`-sweep run from x = 0 and cached on the handle.  Returns (estimate,
+    probe info or None when the cached value was used, probe iterate)."""
+    key = (kw.get("prec", "fp16"), kw.get("eps_inner"))
+    cache = system.__dict__.setdefault("_default_cost", {})
+    if key in cache:
+        return cache[key], None, None
+    x, info = system.solve(b, DEFAULT[0], DEFAULT[1], tol=0.0, maxit_outer=probe, history=True, **kw)
+    slope = _log_rate(system.history) if info["status"] in (gadi.OK, gadi.EMAXIT) else None
+    est = (slope, work(info) / max(1, info["outer_sweeps"]))
+    cache[key] = est
+    return est, info, x
 
 
 def solve_auto(system, A, b, predictor, tol=1e-10, probe=32, **kw):
     """Solve with the predicted (alpha, omega), guarded by the default (0.5, 0.5).
 
-    The prediction runs `probe` sweeps first.  If that run fails (half
-    precision overflow, divergence, breakdown) or its contraction rate, fitted
-    on the last third of the probe, cannot reach `tol` within the remaining
-    sweep budget, the default parameters solve from x = 0 instead; otherwise
-    the prediction continues from its own iterate (warm start), so the guard
-    costs one extra launch and no extra sweeps.  Returns (x, info, used) with
-    used in {'mlp', 'default'}; info sums sweeps, inner steps and device
-    seconds over every launch, and info['fell_back'] = 1 when the default was
-    used."""
+    The prediction runs `probe` sweeps first.  It is kept only if that run
+    neither fails (half-precision overflow, divergence, breakdown) nor, at its
+    fitted contraction rate, needs more work (phases of the solve kernel) to go
+    from its current residual to `tol` than the default parameters would need
+    for the same reduction at their own rate (`default_cost`, measured on the
+    first call for a handle and cached).  A kept prediction continues from its
+    own iterate; otherwise the default continues from that iterate (or from
+    x = 0 after a failed probe).  Returns (x, info, used) with used in {'mlp',
+    'default'}; info sums sweeps, inner steps and device seconds over every
+    launch of the solve (the default's probe, when it runs, is counted in
+    info['guard_seconds']), and info['fell_back'] = 1 when the default was used."""
     a, w = predict(predictor, system, A)
     maxit = kw.pop("maxit_outer", 20000)
     probe = min(probe, maxit)
     total = {"outer_sweeps": 0, "inner_H": 0, "inner_S": 0, "seconds": 0.0, "launches": 0}
+    guard_s = 0.0
 
     def add(info):
         info["launches"] = 1
         for k in total:
             total[k] += info[k]
 
+    def finish(info, used, res_k=1.0):
+        info.update(total)
+        info["relres"] = info["relres"] * res_k
+        info["fell_back"] = int(used == "default")
+        info["guard_seconds"] = guard_s
+        return info
+
     x, info = system.solve(b, a, w, tol=tol, maxit_outer=probe, history=True, **kw)
     add(info)
     if info["status"] == gadi.OK:
-        info.update(total)
-        info["fell_back"] = 0
-        return x, info, "mlp"
+        return x, finish(info, "mlp"), "mlp"
     hist = system.history
-    if info["status"] == gadi.EMAXIT and _projected_sweeps(hist, tol) <= maxit - probe:
-        res_k = hist[-1] if len(hist) else 1.0
-        x, info = system.solve(b, a, w, tol=tol / max(res_k, 1e-300), x0=x, maxit_outer=maxit - probe, **kw)
+    res_k = float(hist[-1]) if len(hist) else 1.0
+    warm = info["status"] == gadi.EMAXIT and np.all(np.isfinite(hist)) and 0.0 < res_k < 1.0
+    keep = False
+    if warm:
+        proj = _projected_sweeps(hist, tol)
+        if proj <= maxit - probe:
+            rest_mlp = proj * work(info) / max(1, info["outer_sweeps"])
+            (slope_d, wps_d), dinfo, xd = default_cost(system, b, probe, **kw)
+            if dinfo is not None:
+                guard_s += dinfo["seconds"]
+            rest_def = (math.log(tol) - math.log(res_k)) / slope_d * wps_d if slope_d else math.inf
+            keep = rest_mlp <= rest_def
+    if keep:
+        x, info = system.solve(b, a, w, tol=tol / res_k, x0=x, maxit_outer=maxit - probe, **kw)
         add(info)
-        info.update(total)
-        info["relres"] = info["relres"] * res_k
-        info["fell_back"] = 0
-        return x, info, "mlp"
+        return x, finish(info, "mlp", res_k), "mlp"
+    if warm:
+        # the default continues from the prediction's iterate (a valid GADI start)
+        x, info = system.solve(b, DEFAULT[0], DEFAULT[1], tol=tol / res_k, x0=x, maxit_outer=maxit, **kw)
+        add(info)
+        return x, finish(info, "default", res_k), "default"
     x, info = system.solve(b, DEFAULT[0], DEFAULT[1], tol=tol, maxit_outer=maxit, **kw)
     add(info)
-    info.update(total)
-    info["fell_back"] = 1
-    return x, info, "default"
+    return x, finish(info, "default"), "default"

@@ -73,3 +73,28 @@ def test_more_than_one_gpu_exits_with_a_message():
                        text=True, timeout=300)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr) or "single" in (r.stdout + r.stderr).lower()
+
+
+def test_survey_byte_model_per_unit():
+    """The CSR per-unit figures: residual 12 z + 22 N, fp16 CG step 6 z + 16 N, CGNE step
+    2 (6 z_s + 8 N), update 18 N (z with the diagonal, z_s without)."""
+    n = 1000
+    z, zs = 7 * n - 600, 6 * n - 600
+    f = lambda s, h, c, l=1: bench.survey_bytes("fp16", z, zs, n, s, h, c, l)
+    assert f(0, 0, 0, 1) == 12 * z + 22 * n
+    assert f(0, 1, 0, 0) == 6 * z + 16 * n
+    assert f(0, 0, 1, 0) == 2 * (6 * zs + 8 * n)
+    assert f(1, 0, 0, 0) == 12 * z + 22 * n + 18 * n
+
+
+def test_parity_tolerance_closed_form():
+    """lambda_min of the h^2-scaled Laplacian and the resulting outer tolerance."""
+    import math
+    import numpy as np
+    import gadi_inputs as gi
+    A = gi.convdiff(8, 3, 10.0)
+    lam = bench.lambda_min_H(A)
+    assert lam == pytest.approx(3 * (2 - 2 * math.cos(math.pi / 9)), rel=1e-15)
+    xs, b = gi.rhs_for(A, "ones")
+    t = bench.parity_tolerance(A, b, xs)
+    assert t == min(1e-10, 0.9 * (1e-8 * lam * np.linalg.norm(xs) / np.linalg.norm(b) - 1e-13))

@@ -226,3 +226,31 @@ def test_solve_auto_falls_back_when_the_prediction_fails():
     x1, i1 = g.solve(b, 0.5, 0.5, tol=1e-10)
     # the default run is the whole solve after the failed probe
     assert info["outer_sweeps"] - i1["outer_sweeps"] <= 32
+
+
+def test_solve_auto_rejects_a_prediction_slower_than_the_default():
+    """A constant prediction alpha = 20, omega = 0.5 converges on this system, but far more slowly
+    than the default (0.5, 0.5) (the right arm of the alpha U-curve).  The old guard kept any
+    prediction that reached the tolerance within the sweep budget; the default judges it now:
+    the default continues from the probe's iterate, converges, and the whole solve costs fewer
+    sweeps than the prediction alone."""
+    from paper_2501_04229_amd import predictor as pr
+    A = gi.convdiff(16, 3, 20.0)
+    g = gadi.System(A)
+    o = oracle.OracleSystem(A)
+    xs, b = gi.rhs_for(A, "uniform", 2)
+    f = g.features(A.dim, A.grid, A.beta)
+    p = _constant_predictor(np.log10(20.0) - pr.log_alpha_ref(f), 0.5)
+    a, w = pr.predict(p, g, A)
+    assert abs(a - 20.0) < 1e-3 * 20.0 and w == 0.5
+    _, slow = g.solve(b, a, w, tol=1e-10)
+    _, fast = g.solve(b, 0.5, 0.5, tol=1e-10)
+    assert slow["status"] == gadi.OK and pr.work(slow) > 2 * pr.work(fast), (slow, fast)
+    x, info, used = pr.solve_auto(g, A, b, p, tol=1e-10)
+    assert used == "default" and info["fell_back"] == 1 and info["status"] == gadi.OK, info
+    assert np.linalg.norm(b - o.spmv("A", x)) <= 1.0000001e-10 * np.linalg.norm(b)
+    assert info["outer_sweeps"] < slow["outer_sweeps"], (info, slow)
+    # the default's cost is measured once per handle and reused
+    assert g._default_cost and info["guard_seconds"] > 0
+    x, info2, used2 = pr.solve_auto(g, A, b, p, tol=1e-10)
+    assert used2 == "default" and info2["guard_seconds"] == 0.0
