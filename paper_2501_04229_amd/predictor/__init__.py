@@ -248,7 +248,7 @@ def solve_auto(system, A, b, predictor, tol=1e-10, probe=32, **kw):
     add(info)
     if info["status"] == gadi.OK:
         return x, finish(info, "mlp"), "mlp"
-    hist = system.history
+    hist = system.history if system.history is not None else np.zeros(0)
     res_k = float(hist[-1]) if len(hist) else 1.0
     warm = info["status"] == gadi.EMAXIT and np.all(np.isfinite(hist)) and 0.0 < res_k < 1.0
     keep = False
