@@ -233,6 +233,8 @@ class System:
             buf = np.zeros(maxit_outer + 1)
             k = _lib.gadi_get_history(self._h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(buf))
             self.history = buf[:k]
+        elif history:
+            self.history = np.zeros(0)
         d = info.as_dict()
         d["status_str"] = status_str(st)
         return x, d

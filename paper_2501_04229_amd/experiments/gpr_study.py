@@ -2,14 +2,14 @@
 
     python -m paper_2501_04229_amd.experiments.gpr_study [--out FILE]
 
-1. Training sets: for small 3-D convection-diffusion systems of the bench's
-   structure (beta = 20, x* ~ U(-1, 1)), the best alpha at omega = 0.5 is
-   found by a coarse log scan of alpha in [0.03, 30] followed by a
-   dichotomous search (evaluate at mid -+ delta, keep the better half) on
-   log10 alpha; the objective is the work of a solve to RES 1e-6 (phases:
-   inner CG steps + 2 CGNE steps + 5 per sweep).  Once with single-precision
-   solves (u_r = u = u_f = single, the paper's FP32 training set) and once
-   with double solves (FP64).
+1. Training sets: for small 3-D convection-diffusion systems of Section
+   4.1's problem (beta = 1 by default, x* ~ U(-1, 1)), the best alpha at
+   omega = 0.5 is found by a coarse log scan of alpha in [0.03, 30] followed
+   by a dichotomous search (evaluate at mid -+ delta, keep the better half)
+   on log10 alpha; the objective is the outer sweeps of a solve to RES 1e-6
+   (or, with --objective work, its phases: inner CG steps + 2 CGNE steps + 5
+   per sweep).  Once with single-precision solves (u_r = u = u_f = single,
+   the paper's FP32 training set) and once with double solves (FP64).
 2. GPR of log10 alpha on log2 n (libgadi's gadi_gpr_*), extrapolated to
    n = 32, 64, 128 with the paper's retraining: each prediction joins the
    training set before the next size.  Table pred32 compares the alphas
@@ -41,59 +41,39 @@ import paper_2501_04229_amd as gadi  # noqa: E402
 from paper_2501_04229_amd import predictor as pr  # noqa: E402
 from paper_2501_04229_amd.predictor import gpr  # noqa: E402
 
-BETA = 20.0
+BETA = [1.0]  # Section 4.1's problem; --beta changes it
 OMEGA = 0.5
 
 
 def system(n, device):
     import torch
-    A = gi.convdiff(n, 3, BETA)
+    A = gi.convdiff(n, 3, BETA[0])
     _, b = gi.rhs_for(A, "uniform", 0)
     return A, gadi.System(A), torch.from_numpy(b).to(device)
 
 
-def best_alpha(g, b, prec, tol, maxit, maxit_inner, coarse=7, delta=0.01, width=0.08):
-    """Coarse scan of log10 alpha in [-1.5, 1.5], then a dichotomous search
-    around the best scan point.  A solve that fails or exceeds the sweep or
-    inner-step caps counts as infinite work.  Returns (alpha, work,
-    evaluations)."""
-    cache = {}
-
+def best_alpha(g, b, prec, tol, maxit, maxit_inner, objective):
+    """Near-optimal alpha at omega = 0.5 by the dichotomy search of
+    predictor.gpr.dichotomy_search; the cost of a solve is its outer sweeps
+    (objective 'sweeps') or its phases (objective 'work'); a failed solve or
+    one beyond the sweep or inner-step caps costs infinity.  Returns (alpha,
+    cost, evaluations)."""
     def f(u):
-        key = round(u, 6)
-        if key not in cache:
-            _, info = g.solve(b, 10.0 ** u, OMEGA, tol=tol, prec=prec, maxit_outer=maxit,
-                              maxit_inner=maxit_inner)
-            cache[key] = pr.work(info) if info["status"] == gadi.OK else math.inf
-        return cache[key]
-
-    grid = np.linspace(-1.5, 1.5, coarse)
-    vals = [f(u) for u in grid]
-    k = int(np.argmin(vals))
-    lo, hi = grid[max(k - 1, 0)], grid[min(k + 1, coarse - 1)]
-    if not math.isfinite(vals[k]):
-        return math.nan, math.inf, len(cache)
-    while hi - lo > width:
-        mid = 0.5 * (lo + hi)
-        a, c = f(mid - delta), f(mid + delta)
-        if a < c:
-            hi = mid + delta
-        elif c < a:
-            lo = mid - delta
-        else:
-            lo, hi = mid - delta, mid + delta
-    cand = {u: v for u, v in cache.items() if lo - 1e-9 <= u <= hi + 1e-9} or cache
-    u_best = min(cand, key=lambda u: (cand[u], -u))
-    return 10.0 ** u_best, cache[u_best], len(cache)
+        _, info = g.solve(b, 10.0 ** u, OMEGA, tol=tol, prec=prec, maxit_outer=maxit, maxit_inner=maxit_inner)
+        if info["status"] != gadi.OK:
+            return math.inf
+        return info["outer_sweeps"] if objective == "sweeps" else pr.work(info)
+    u, cost, ev = gpr.dichotomy_search(f)
+    return 10.0 ** u, cost, ev
 
 
-def training(sizes, device, tol, maxit, maxit_inner):
+def training(sizes, device, tol, maxit, maxit_inner, objective):
     rows = []
     for n in sizes:
         A, g, b = system(n, device)
         for prec, name in (("s-s-s", "fp32"), ("fp64", "fp64")):
             t0 = time.time()
-            a, w, ev = best_alpha(g, b, prec, tol, maxit, maxit_inner)
+            a, w, ev = best_alpha(g, b, prec, tol, maxit, maxit_inner, objective)
             rows.append({"n": n, "prec": name, "alpha": a, "work": w, "evaluations": ev,
                          "wall_seconds": time.time() - t0})
             print(f"[train] n={n} {name}: alpha* {a:.4g} (work {w:.0f}, {ev} solves, {time.time() - t0:.1f} s)",
@@ -130,8 +110,11 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--maxit", type=int, default=400)
     ap.add_argument("--maxit-inner", type=int, default=300)
+    ap.add_argument("--beta", type=float, default=1.0)
+    ap.add_argument("--objective", default="sweeps", choices=["sweeps", "work"])
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
+    BETA[0] = a.beta
     import torch
     if not torch.cuda.is_available():
         raise SystemExit("the GPR study runs on the GPU")
@@ -139,7 +122,7 @@ def main():
     sizes = [int(s) for s in a.sizes.split(",")]
     targets = [int(s) for s in a.targets.split(",")]
     t0 = time.time()
-    train = training(sizes, dev, a.tol, a.maxit, a.maxit_inner)
+    train = training(sizes, dev, a.tol, a.maxit, a.maxit_inner, a.objective)
     pred = {n: {} for n in targets}
     table = []
     for name in ("fp64", "fp32"):
@@ -151,8 +134,14 @@ def main():
             print(f"[gpr] {name} training set -> n={n}: alpha {al:.4f} (sd of log10 alpha {sd:.3f})", flush=True)
     mlp = pr.load() if os.path.exists(pr.WEIGHTS) else None
     applied = apply(targets, pred, dev, mlp)
-    res = {"training": train, "pred32": table, "apply": applied, "omega": OMEGA, "beta": BETA,
-           "train_tol": a.tol, "wall_seconds": time.time() - t0}
+    paper = {32: 0.0699, 64: 0.0599, 128: 0.0595}  # Table pred32 (both training sets)
+    for row in table:
+        row["paper_alpha"] = paper.get(row["n"])
+    same = all(abs(math.log10(pred[n]["fp32"] / pred[n]["fp64"])) <= 0.08 for n in targets
+               if "fp32" in pred[n] and "fp64" in pred[n])
+    res = {"training": train, "pred32": table, "fp32_equals_fp64_within_search_width": same, "apply": applied,
+           "omega": OMEGA, "beta": BETA[0], "objective": a.objective, "train_tol": a.tol,
+           "wall_seconds": time.time() - t0}
     if a.out:
         with open(a.out, "w") as f:
             json.dump(res, f, indent=1)

@@ -68,3 +68,42 @@ def predict_alpha(sizes, alphas, targets, retrain=True):
             xs.append(float(np.log2(n)))
             ys.append(float(m[0]))
     return out
+
+
+def dichotomy_search(f, lo=-1.5, hi=1.5, coarse=7, delta=0.01, width=0.08):
+    """Near-optimal log10 alpha of one small system (Section 3.3 finds the
+    training set's alphas by a dichotomy search): f(u) is the cost of a solve
+    with alpha = 10^u (infinite for a failed solve).  A coarse scan of `coarse`
+    points over [lo, hi] brackets the best scan point by its neighbours; then,
+    while the bracket is wider than `width` decades, f is compared at mid -+
+    delta and the better half is kept (both halves' inner ends when they tie).
+    Returns (u, f(u), evaluations) for the cheapest evaluated point inside the
+    final bracket, ties going to the larger alpha; (nan, inf, evaluations) when
+    every scan point failed."""
+    import math
+    cache = {}
+
+    def ev(u):
+        key = round(float(u), 9)
+        if key not in cache:
+            cache[key] = float(f(key))
+        return cache[key]
+
+    grid = np.linspace(lo, hi, coarse)
+    vals = [ev(u) for u in grid]
+    k = int(np.argmin(vals))
+    if not math.isfinite(vals[k]):
+        return math.nan, math.inf, len(cache)
+    a, c = grid[max(k - 1, 0)], grid[min(k + 1, coarse - 1)]
+    while c - a > width:
+        mid = 0.5 * (a + c)
+        fl, fr = ev(mid - delta), ev(mid + delta)
+        if fl < fr:
+            c = mid + delta
+        elif fr < fl:
+            a = mid - delta
+        else:
+            a, c = mid - delta, mid + delta
+    inside = {u: v for u, v in cache.items() if a - 1e-9 <= u <= c + 1e-9} or cache
+    u_best = min(inside, key=lambda u: (inside[u], -u))
+    return u_best, cache[u_best], len(cache)

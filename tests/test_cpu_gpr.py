@@ -62,3 +62,18 @@ def test_retraining_adds_each_prediction():
     assert out[0][1] == pytest.approx(10 ** m32[0], rel=1e-9)
     m64, _ = ogpr.predict(ogpr.fit(xs + [5.0], ys + [m32[0]]), [6.0])
     assert out[1][1] == pytest.approx(10 ** m64[0], rel=1e-9)
+
+
+def test_dichotomy_search_on_known_costs():
+    """The search of Section 3.3's training-set generation on costs with a known minimiser:
+    a smooth bowl, an integer-valued (flat) bowl, failures beyond a threshold, and all-failed."""
+    import math
+    from paper_2501_04229_amd.predictor.gpr import dichotomy_search
+    u, v, ev = dichotomy_search(lambda u: (u - 0.37) ** 2)
+    assert abs(u - 0.37) <= 0.08 and ev <= 7 + 2 * 10
+    u, v, _ = dichotomy_search(lambda u: math.floor(40 * abs(u + 0.9)))
+    assert abs(u + 0.9) <= 0.08 and v <= math.floor(40 * 0.08)
+    u, v, _ = dichotomy_search(lambda u: math.inf if u < -0.4 else (u + 0.3) ** 2)
+    assert abs(u + 0.3) <= 0.1
+    u, v, _ = dichotomy_search(lambda u: math.inf)
+    assert math.isnan(u) and v == math.inf

@@ -229,7 +229,7 @@ def test_solve_auto_falls_back_when_the_prediction_fails():
 
 
 def test_solve_auto_rejects_a_prediction_slower_than_the_default():
-    """A constant prediction alpha = 20, omega = 0.5 converges on this system, but far more slowly
+    """A constant prediction alpha = 8, omega = 0.5 converges on this system, but far more slowly
     than the default (0.5, 0.5) (the right arm of the alpha U-curve).  The old guard kept any
     prediction that reached the tolerance within the sweep budget; the default judges it now:
     the default continues from the probe's iterate, converges, and the whole solve costs fewer
@@ -240,9 +240,9 @@ def test_solve_auto_rejects_a_prediction_slower_than_the_default():
     o = oracle.OracleSystem(A)
     xs, b = gi.rhs_for(A, "uniform", 2)
     f = g.features(A.dim, A.grid, A.beta)
-    p = _constant_predictor(np.log10(20.0) - pr.log_alpha_ref(f), 0.5)
+    p = _constant_predictor(np.log10(8.0) - pr.log_alpha_ref(f), 0.5)
     a, w = pr.predict(p, g, A)
-    assert abs(a - 20.0) < 1e-3 * 20.0 and w == 0.5
+    assert abs(a - 8.0) < 1e-3 * 8.0 and w == 0.5
     _, slow = g.solve(b, a, w, tol=1e-10)
     _, fast = g.solve(b, 0.5, 0.5, tol=1e-10)
     assert slow["status"] == gadi.OK and pr.work(slow) > 2 * pr.work(fast), (slow, fast)
