@@ -139,6 +139,25 @@ gadi_status gadi_set_stream(gadi_handle* h, void* stream);
 gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x, double alpha, double omega,
                           double tol, const gadi_options* opts, gadi_solve_info* info);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve of
+ * gadi_ir_solve with the same kernels and results, its workspace taken from a
+ * fixed file-scope device array of 256 MiB per device instead of memory the
+ * handle allocates.  No hipMalloc, hipFree or allocating library call is made.
+ * Restrictions: b and x are device pointers (opts->on_device must be 1; with
+ * opts == NULL the FP16-IR defaults apply to device pointers), prec is
+ * GADI_PREC_FP16_IR or GADI_PREC_FP64 (the operators gadi_setup stores), and
+ * record_history must be 0.  The launch shape is the one gadi_ir_solve's
+ * autotuner chose for this handle and precision, else one 1024-thread block per
+ * compute unit with the one-reduction inner solves.  ENOMEM (nothing enqueued)
+ * if the padded system needs more than the array holds: 104 bytes per padded
+ * row plus 1 MiB, i.e. at most 2,573,753 padded rows.  info->seconds is not
+ * measured (0).  Every call on a device shares that device's array: calls that
+ * overlap on one device (several handles or streams) race; each call clears the
+ * array's vectors before use and synchronises its stream before returning. */
+gadi_status gadi_ir_solve_noalloc(gadi_handle* h, const double* b, double* x, double alpha, double omega,
+                                  double tol, const gadi_options* opts, gadi_solve_info* info);
+
 /* RES history of the last solve with record_history = 1: copies up to `cap`
  * values (RES before each sweep) into `out` (host) and returns the count. */
 int32_t gadi_get_history(gadi_handle* h, double* out, int32_t cap);

@@ -68,6 +68,7 @@ def _load():
         "gadi_setup": (i32, [P(_Csr), ctypes.c_int, P(vp)]),
         "gadi_set_stream": (i32, [vp, vp]),
         "gadi_ir_solve": (i32, [vp, vp, vp, f64, f64, f64, P(_Options), P(SolveInfo)]),
+        "gadi_ir_solve_noalloc": (i32, [vp, vp, vp, f64, f64, f64, P(_Options), P(SolveInfo)]),
         "gadi_get_history": (i32, [vp, P(f64), i32]),
         "gadi_ir_solve_batched": (i32, [P(vp), i32, P(vp), P(vp), P(f64), P(f64), i32, f64, P(_Options),
                                         P(SolveInfo)]),
@@ -238,6 +239,25 @@ class System:
         d = info.as_dict()
         d["status_str"] = status_str(st)
         return x, d
+
+    def solve_noalloc(self, b, x, alpha=0.5, omega=0.5, tol=1e-10, prec="fp16", eps_inner=None,
+                      maxit_outer=20000, maxit_inner=2000):
+        """gadi_ir_solve_noalloc: the solve with the library's fixed scratch array as
+        workspace (no device allocation).  b, x: float64 CUDA tensors of length n; x
+        is the start and receives the result.  Returns the info dict."""
+        if not (_is_device_tensor(b) and _is_device_tensor(x)):
+            raise ValueError("solve_noalloc takes device tensors")
+        if len(b) != self.n or len(x) != self.n:
+            raise ValueError("b and x must have length n")
+        self.bind_current_stream()
+        o = options(prec, eps_inner, maxit_outer, maxit_inner, True, False)
+        info = SolveInfo()
+        st = _lib.gadi_ir_solve_noalloc(self._h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                        float(alpha), float(omega), float(tol), ctypes.byref(o), ctypes.byref(info))
+        d = info.as_dict()
+        d["status"] = st
+        d["status_str"] = status_str(st)
+        return d
 
     def spmv(self, which: str, x, y, alpha=1.0):
         """Device product on torch tensors: which in {'A','H16','S16','H64','H8'}."""

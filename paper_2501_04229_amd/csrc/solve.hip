@@ -195,6 +195,17 @@ static gadi_status launch_solve(System& s, int prec, const SolveArgs& a, int blo
   return fused ? launch_prec<true>(s, prec, a, block, per_cu) : launch_prec<false>(s, prec, a, block, per_cu);
 }
 
+// for the allocation-free entry point (noalloc.hip): the same launch with the
+// synchronisation state and vectors the caller's SolveArgs name
+gadi_status launch_solve_shape(System& s, int prec, SolveArgs a, int block, int per_cu, bool fused) {
+  gadi_status st = device_props();
+  if (st != GADI_OK) return st;
+  a.timeout = barrier_timeout_ticks();
+  return launch_solve(s, prec, a, block, per_cu, fused);
+}
+
+double wall_clock_hz() { return (double)g_wall_rate_khz * 1000.0; }
+
 // solution stored in single precision (u = single)
 static bool single_solution(int prec) { return prec == GADI_PREC_H_S_S || prec == GADI_PREC_S_S_S; }
 // residual in single precision (u_f = single)

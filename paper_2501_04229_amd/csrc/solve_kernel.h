@@ -69,7 +69,7 @@ static gadi_status launch_t(System& s, SolveArgs a, int per_cu) {
   if (G > kMaxBlocks) G = kMaxBlocks;
   if (G < 1) G = 1;
   a.ntiles = ntiles;
-  hipLaunchKernelGGL(reset_sync_kernel, dim3(32), dim3(1024), 0, s.stream, s.sync, s.flags, s.info, a.prof);
+  hipLaunchKernelGGL(reset_sync_kernel, dim3(32), dim3(1024), 0, s.stream, a.sync, a.flags, a.info, a.prof);
   GADI_HIP_CHECK(hipGetLastError());
   void* kargs[] = {(void*)&a};
   GADI_HIP_CHECK(hipLaunchCooperativeKernel((const void*)solve_kernel<Mode, BLOCK, FUSED, PW>, dim3((unsigned)G), dim3(BLOCK),
