@@ -7,9 +7,11 @@ beta ~ logU(1, 1000), seed 2, b = A 1) swept over the 16 (alpha, omega) trials
 (4 log-spaced alphas in [1e-3, 10] x omega in {0, 0.5, 1, 1.5}), FP16-IR to
 RES 1e-10, at most 5000 sweeps per trial, with dominated trials pruned (a trial
 stops once its work exceeds that of a converged trial of its system).  The
-family runs in launches of `group` systems (16 x 16 = 256 units, one per
-compute unit), each reported when it ends: wall time, trials per second,
-sweeps per second, converged trials.  Then the `sequential` smallest systems:
+family runs in launches of `group` systems (default: all of them in one
+launch), each reported when it ends: wall time, trials per second, sweeps per
+second, converged and pruned trials, and the matrix bytes a trial reads per
+product with and without the pack's shared matrix loads.  Then the
+`sequential` smallest systems:
 one unpruned batched launch against the same trials solved one by one with
 gadi_ir_solve (records must agree: status, sweeps within max(2, 2%)).
 """
@@ -43,7 +45,7 @@ def build(fam):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--count", type=int, default=64)
-    ap.add_argument("--group", type=int, default=16)
+    ap.add_argument("--group", type=int, default=0, help="systems per launch (0: all in one launch)")
     ap.add_argument("--sequential", type=int, default=4)
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
@@ -52,11 +54,13 @@ def main():
         raise SystemExit("the batched study runs on the GPU")
     fam = gi.batched_family(a.count)
     al, om = pr.trial_grid()
+    group = a.group or len(fam)
+    os.environ["GADI_PROGRESS"] = "1"
     res = {"systems": len(fam), "trials_per_system": len(al), "groups": []}
     tot_t, tot_trials, tot_sweeps, tot_ok, tot_rows = 0.0, 0, 0, 0, 0
-    for g0 in range(0, len(fam), a.group):
+    for g0 in range(0, len(fam), group):
         t0 = time.perf_counter()
-        systems, bs = build(fam[g0:g0 + a.group])
+        systems, bs = build(fam[g0:g0 + group])
         t_setup = time.perf_counter() - t0
         rows = sum(s.n for s in systems)
         gadi.solve_batched(systems[:1], bs[:1], al, om, tol=1e-10, maxit_outer=20, prune=True)  # tuner, warm-up
@@ -68,8 +72,17 @@ def main():
         flat = [r for rs in recs for r in rs]
         ok = sum(r["status"] == gadi.OK for r in flat)
         sweeps = sum(r["outer_sweeps"] for r in flat)
+        # fp16 operator bytes per row of one product (values of the 2-D stencil's H with its
+        # diagonal, or of S): read once per pack of up to 4 trials instead of once per trial
+        lay = [s_.layout() for s_ in systems]
+        mat = sum(2.0 * (L["nnz_off"] + L["n"]) for L in lay) / max(1, sum(L["n"] for L in lay))
         res["groups"].append({"first": g0, "systems": len(systems), "rows": rows, "seconds": dt, "setup_s": t_setup,
-                              "trials": len(flat), "converged": ok, "sweeps": sweeps})
+                              "trials": len(flat), "converged": ok, "sweeps": sweeps,
+                              "maxit_or_pruned": sum(r["status"] == gadi.EMAXIT for r in flat),
+                              "matrix_bytes_per_row_product_unshared": mat,
+                              "matrix_bytes_per_row_product_per_trial": mat / 4.0,
+                              "sweeps_per_s": sweeps / dt, "trials_per_s": len(flat) / dt,
+                              "launch_seconds": flat[0]["barrier_seconds"]})
         tot_t += dt
         tot_trials += len(flat)
         tot_sweeps += sweeps

@@ -229,23 +229,29 @@ def test_solve_auto_falls_back_when_the_prediction_fails():
 
 
 def test_solve_auto_rejects_a_prediction_slower_than_the_default():
-    """A constant prediction alpha = 8, omega = 0.5 converges on this system, but far more slowly
-    than the default (0.5, 0.5) (the right arm of the alpha U-curve).  The old guard kept any
-    prediction that reached the tolerance within the sweep budget; the default judges it now:
-    the default continues from the probe's iterate, converges, and the whole solve costs fewer
-    sweeps than the prediction alone."""
+    """A constant prediction that converges, but needs more than twice the default's work (an
+    alpha far off the optimum of the alpha U-curve, picked among a few candidates by measuring
+    them).  The old guard kept any prediction that reached the tolerance within the sweep budget;
+    the default judges it now: the default continues from the probe's iterate, converges, and the
+    whole solve costs fewer sweeps than the prediction alone."""
     from paper_2501_04229_amd import predictor as pr
     A = gi.convdiff(16, 3, 20.0)
     g = gadi.System(A)
     o = oracle.OracleSystem(A)
     xs, b = gi.rhs_for(A, "uniform", 2)
     f = g.features(A.dim, A.grid, A.beta)
-    p = _constant_predictor(np.log10(8.0) - pr.log_alpha_ref(f), 0.5)
-    a, w = pr.predict(p, g, A)
-    assert abs(a - 8.0) < 1e-3 * 8.0 and w == 0.5
-    _, slow = g.solve(b, a, w, tol=1e-10)
     _, fast = g.solve(b, 0.5, 0.5, tol=1e-10)
-    assert slow["status"] == gadi.OK and pr.work(slow) > 2 * pr.work(fast), (slow, fast)
+    assert fast["status"] == gadi.OK
+    slow = None
+    for a_slow in (0.1, 0.05, 0.03, 8.0):
+        _, rec = g.solve(b, a_slow, 0.5, tol=1e-10)
+        if rec["status"] == gadi.OK and pr.work(rec) > 2 * pr.work(fast):
+            slow = rec
+            break
+    assert slow is not None, "no slower converging alpha among the candidates"
+    p = _constant_predictor(np.log10(a_slow) - pr.log_alpha_ref(f), 0.5)
+    a, w = pr.predict(p, g, A)
+    assert abs(a - a_slow) < 1e-3 * a_slow and w == 0.5
     x, info, used = pr.solve_auto(g, A, b, p, tol=1e-10)
     assert used == "default" and info["fell_back"] == 1 and info["status"] == gadi.OK, info
     assert np.linalg.norm(b - o.spmv("A", x)) <= 1.0000001e-10 * np.linalg.norm(b)
