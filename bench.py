@@ -304,6 +304,44 @@ def measure_sub(workload, args, pred):
     return out
 
 
+def learned_gain(pred, count=8, seed=5, nmin=64, nmax=96):
+    """What the network gains: solve_auto (prediction judged by the default)
+    against plain default-parameter FP16-IR on `count` fresh 3-D systems of the
+    evaluation family's kind (n in [nmin, nmax], beta ~ logU(1, 500)), device
+    seconds including the guard's probes; geometric means."""
+    import torch
+    import gadi_inputs as gi
+    import paper_2501_04229_amd as gadi
+    from paper_2501_04229_amd import predictor as pr
+    rows = []
+    for n, dim, beta, sd in gi.test_family(count, seed=seed, nmin=nmin, nmax=nmax):
+        A = gi.convdiff(n, dim, beta)
+        _, b = gi.rhs_for(A, "uniform", sd)
+        g = gadi.System(A)
+        bd = torch.from_numpy(b).cuda()
+        g.solve(bd, 0.5, 0.5, tol=1e-10, maxit_outer=3)  # launch-shape tuning
+        _, idf = g.solve(bd, 0.5, 0.5, tol=1e-10)
+        _, iau, used = pr.solve_auto(g, A, bd, pred, tol=1e-10)
+        rows.append({"n": n, "beta": float(beta), "used": used, "status_default": idf["status_str"],
+                     "status_auto": iau["status_str"], "sweeps_default": idf["outer_sweeps"],
+                     "sweeps_auto": iau["outer_sweeps"], "seconds_default": idf["seconds"],
+                     "seconds_auto": iau["seconds"] + iau["guard_seconds"]})
+        g.close()
+    gm = lambda v: float(math.exp(np.mean(np.log(v))))
+    out = {"systems": rows, "subset": f"{count} 3-D systems, n in [{nmin}, {nmax}], beta ~ logU(1, 500), seed {seed}",
+           "gmean_seconds_default": gm([r["seconds_default"] for r in rows]),
+           "gmean_seconds_auto": gm([r["seconds_auto"] for r in rows]),
+           "gmean_sweeps_default": gm([r["sweeps_default"] for r in rows]),
+           "gmean_sweeps_auto": gm([r["sweeps_auto"] for r in rows]),
+           "failures": sum(r["status_auto"] != "ok" for r in rows),
+           "fallbacks": sum(r["used"] != "mlp" for r in rows)}
+    out["time_gain"] = out["gmean_seconds_default"] / out["gmean_seconds_auto"]
+    log(f"learned gain on {count} fresh systems: {out['time_gain']:.3f}x device time "
+        f"({out['gmean_sweeps_default']:.0f} -> {out['gmean_sweeps_auto']:.0f} sweeps), "
+        f"{out['fallbacks']} fallbacks, {out['failures']} failures")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +358,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-spmv", action="store_true", help="skip the stand-alone product timing (graph replays)")
     ap.add_argument("--no-parity-tol", action="store_true", help="skip the solves at the parity tolerance")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-gain subset")
     ap.add_argument("--cpu-threads", type=int, default=0, help="OpenMP threads of the oracle timing (0: all)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with one elementwise copy of 2^26 floats (reads and writes 256 MiB) "
@@ -365,6 +404,15 @@ def main():
     prof = g.phase_profile()
     log("phase profile (block 0 compute s, count): " +
         ", ".join(f"{k} {v[0]:.4f}/{v[1]}" for k, v in prof.items() if v[1]))
+    bw, bt = g.block_profile()
+    blocks = None
+    if len(bt):
+        comp = bt - bw
+        q = lambda v: {"min": float(np.min(v)), "median": float(np.median(v)), "max": float(np.max(v)),
+                       "argmin": int(np.argmin(v)), "argmax": int(np.argmax(v))}
+        blocks = {"compute_seconds": q(comp), "barrier_seconds": q(bw), "launch_seconds": float(np.max(bt))}
+        log(f"per-block compute s (last launch): min {np.min(comp):.4f} median {np.median(comp):.4f} "
+            f"max {np.max(comp):.4f}; in barriers: min {np.min(bw):.4f} max {np.max(bw):.4f}")
     xh = x.cpu().numpy()
     rel_err_xstar = float(np.linalg.norm(xh - xs) / np.linalg.norm(xs))
     lay = g.layout()
@@ -421,6 +469,10 @@ def main():
         sp = spmv_gbs(g, A, alpha)
         log(f"spmv: {sp}")
 
+    learned = None
+    if pred is not None and not args.no_learned:
+        learned = learned_gain(pred)
+
     cpu = None
     if not args.no_cpu:
         sweeps_needed = fp64["inner_1e-6"]["sweeps"] if fp64 else info["outer_sweeps"]
@@ -475,6 +527,7 @@ def main():
         "speedup_vs_fp64_gadi": speed,
         "spmv": sp,
         "phase_profile_last_launch": {k: {"seconds": v[0], "count": v[1]} for k, v in prof.items() if v[1]},
+        "block_profile_last_launch": blocks,
         "roofline": {"bound": "hbm", "kernel": f"solve_kernel<{args.prec}>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "algorithmic_bytes_per_launch": sm["algorithmic_bytes"] / launches,
@@ -484,6 +537,7 @@ def main():
                      "launches": launches, "launch_seconds_mean": launch_s, "traffic": None},
         "cpu_baseline": cpu,
         "sub_record": sub,
+        "learned_gain": learned,
     }
     traffic, tsrc = profiled_traffic(args.workload, args.prec)
     out["roofline"]["traffic"] = traffic

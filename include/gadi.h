@@ -158,6 +158,12 @@ gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x, double alp
 gadi_status gadi_ir_solve_noalloc(gadi_handle* h, const double* b, double* x, double alpha, double omega,
                                   double tol, const gadi_options* opts, gadi_solve_info* info);
 
+/* Per-block timing of the last gadi_ir_solve launch, for load-balance
+ * studies: wait_seconds[i] the time block i spent inside device-wide barriers,
+ * total_seconds[i] its time in the launch (host arrays of `cap` entries, either
+ * may be NULL).  Returns the number of blocks filled (0 if none). */
+int32_t gadi_get_block_profile(gadi_handle* h, double* wait_seconds, double* total_seconds, int32_t cap);
+
 /* RES history of the last solve with record_history = 1: copies up to `cap`
  * values (RES before each sweep) into `out` (host) and returns the count. */
 int32_t gadi_get_history(gadi_handle* h, double* out, int32_t cap);

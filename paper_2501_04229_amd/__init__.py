@@ -77,6 +77,7 @@ def _load():
         "gadi_get_split_fp8": (i32, [vp, i32, vp, vp, vp, P(i64)]),
         "gadi_get_layout": (i32, [vp, P(i64)]),
         "gadi_get_phase_profile": (i32, [vp, P(f64), P(i64)]),
+        "gadi_get_block_profile": (i32, [vp, P(f64), P(f64), i32]),
         "gadi_features": (i32, [vp, i32, i32, P(f64), P(ctypes.c_float)]),
         "gadi_mlp_create": (i32, [ctypes.c_uint64, P(vp)]),
         "gadi_mlp_destroy": (i32, [vp]),
@@ -301,6 +302,14 @@ class System:
         cnt = (ctypes.c_int64 * 10)()
         _check(_lib.gadi_get_phase_profile(self._h, sec, cnt), "gadi_get_phase_profile")
         return {k: (sec[i], cnt[i]) for i, k in enumerate(self.PHASES)}
+
+    def block_profile(self):
+        """(seconds inside barriers, seconds in the launch) per block of the last solve launch."""
+        w = np.zeros(4096)
+        t = np.zeros(4096)
+        k = _lib.gadi_get_block_profile(self._h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 4096)
+        return w[:k], t[:k]
 
     def layout(self):
         """Packed layout counts: dict with n, npad, nnz_off, slots, dia_slots,

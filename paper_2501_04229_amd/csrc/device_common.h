@@ -257,7 +257,7 @@ struct Grid {
   unsigned nblocks;
   unsigned long long epoch;
   long long timeout;
-  long long wait_ticks;  // block 0: wall-clock ticks spent inside barriers
+  long long wait_ticks;  // thread 0: wall-clock ticks this block spent inside barriers
 };
 
 struct Red4 {
@@ -271,7 +271,7 @@ static __device__ __forceinline__ Red4 grid_allreduce(Grid& g, double s0, double
   __shared__ double sh[NW][4];
   __shared__ int sh_abort;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const long long t_enter = (blockIdx.x == 0 && tid == 0) ? wall_clock64() : 0;
+  const long long t_enter = tid == 0 ? wall_clock64() : 0;
   {
     const double a0 = wave_sum(s0), a1 = wave_sum(s1), a2 = wave_sum(s2), a3 = wave_max(m3);
     if (lane == 0) {
@@ -387,7 +387,7 @@ static __device__ __forceinline__ Red4 grid_allreduce(Grid& g, double s0, double
   out.v[2] = r[2];
   out.v[3] = r[3];
   ok = sh_abort == 0;
-  if (blockIdx.x == 0 && tid == 0) g.wait_ticks += wall_clock64() - t_enter;
+  if (tid == 0) g.wait_ticks += wall_clock64() - t_enter;
   __syncthreads();  // shared state is rewritten by the next call
   return out;
 }

@@ -26,6 +26,10 @@ constexpr int kPadRows = kTile;
 constexpr int kMaxBlocks = 4096;
 // Stride between per-block arrival flags (one 64-byte line each).
 constexpr int kFlagStride = 8;
+// Per-phase profile of block 0 (ticks [10], counts [10]), then per block the
+// ticks inside barriers [kMaxBlocks] and in the whole launch [kMaxBlocks].
+constexpr int kProfHead = 20;
+constexpr int kProfLen = kProfHead + 2 * 4096;
 // Largest number of distinct column offsets of a diagonal-style slice.
 constexpr int kDiaMax = 8;
 // largest system: its padded double vectors stay below 4 GiB
@@ -118,7 +122,7 @@ struct System {
   double* part = nullptr;    // [2][kMaxBlocks][4]
   double* result = nullptr;  // [2][4]
   DevInfo* info = nullptr;
-  long long* prof = nullptr;  // [20] per-phase profile of the last solve
+  long long* prof = nullptr;  // [kProfLen] per-phase and per-block profile of the last solve
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // launch shape of the solve kernel per precision mode, chosen by the autotuner
   int tuned_block[7] = {0, 0, 0, 0, 0, 0, 0};

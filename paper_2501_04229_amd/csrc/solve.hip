@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <map>
 #include <tuple>
+#include <vector>
 
 #include "solve_kernel.h"
 
@@ -57,8 +58,8 @@ gadi_status ensure_workspace(System& s) {
   GADI_HIP_CHECK(hipMalloc((void**)&s.flags, sizeof(unsigned long long) * kMaxBlocks * kFlagStride));
   GADI_HIP_CHECK(hipMalloc((void**)&s.result, sizeof(double) * 8));
   GADI_HIP_CHECK(hipMalloc((void**)&s.info, sizeof(DevInfo)));
-  GADI_HIP_CHECK(hipMalloc((void**)&s.prof, sizeof(long long) * 20));
-  GADI_HIP_CHECK(hipMemset(s.prof, 0, sizeof(long long) * 20));
+  GADI_HIP_CHECK(hipMalloc((void**)&s.prof, sizeof(long long) * kProfLen));
+  GADI_HIP_CHECK(hipMemset(s.prof, 0, sizeof(long long) * kProfLen));
   GADI_HIP_CHECK(hipEventCreate(&s.ev0));
   GADI_HIP_CHECK(hipEventCreate(&s.ev1));
   return GADI_OK;
@@ -444,4 +445,20 @@ extern "C" int32_t gadi_solver_blocks(gadi_handle* h, int32_t* threads) {
   if (!h) return 0;
   if (threads) *threads = h->sys.last_block_threads;
   return h->sys.last_blocks;
+}
+
+extern "C" int32_t gadi_get_block_profile(gadi_handle* h, double* wait_seconds, double* total_seconds, int32_t cap) {
+  if (!h || !h->sys.prof || h->sys.last_blocks <= 0) return 0;
+  const int nb = h->sys.last_blocks < cap ? h->sys.last_blocks : cap;
+  if (nb <= 0) return 0;
+  std::vector<long long> buf(2 * kMaxBlocks);
+  if (hipMemcpy(buf.data(), h->sys.prof + kProfHead, sizeof(long long) * 2 * kMaxBlocks, hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return 0;
+  const double hz = (double)g_wall_rate_khz * 1000.0;
+  for (int i = 0; i < nb; ++i) {
+    if (wait_seconds) wait_seconds[i] = (double)buf[i] / hz;
+    if (total_seconds) total_seconds[i] = (double)buf[kMaxBlocks + i] / hz;
+  }
+  return nb;
 }

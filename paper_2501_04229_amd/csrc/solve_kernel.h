@@ -14,6 +14,7 @@ int num_cus();
 // layout with PW offsets per slice (SolveArgs::dia_u).
 template <class Mode, int BLOCK, bool FUSED, int PW>
 __global__ void __launch_bounds__(BLOCK) solve_kernel(SolveArgs a) {
+  const long long t_begin = wall_clock64();
   GridRed<BLOCK> red{Grid{a.sync, a.flags, a.part, a.result, gridDim.x, 0ull, a.timeout, 0ll}};
   const unsigned lb = logical_block(blockIdx.x, gridDim.x);
   const int t0 = (int)((long long)a.ntiles * lb / gridDim.x);
@@ -32,6 +33,11 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(SolveArgs a) {
     ok = solve_body<Mode, BLOCK, FUSED, Mode::tiles>(a, red, pat, t0, t1, r);
   }
   if (!ok) return;
+  // per-block profile: ticks inside barriers and in the whole launch
+  if (a.prof && threadIdx.x == 0) {
+    a.prof[kProfHead + blockIdx.x] = red.g.wait_ticks;
+    a.prof[kProfHead + kMaxBlocks + blockIdx.x] = wall_clock64() - t_begin;
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     r.barriers = (long long)red.g.epoch;
     r.barrier_ticks = red.g.wait_ticks;

@@ -242,8 +242,10 @@ def solve_auto(system, A, b, predictor, tol=1e-10, probe=32, **kw):
         info["relres"] = info["relres"] * res_k
         info["fell_back"] = int(used == "default")
         info["guard_seconds"] = guard_s
+        info["guard"] = guard
         return info
 
+    guard = {}
     x, info = system.solve(b, a, w, tol=tol, maxit_outer=probe, history=True, **kw)
     add(info)
     if info["status"] == gadi.OK:
@@ -252,8 +254,10 @@ def solve_auto(system, A, b, predictor, tol=1e-10, probe=32, **kw):
     res_k = float(hist[-1]) if len(hist) else 1.0
     warm = info["status"] == gadi.EMAXIT and np.all(np.isfinite(hist)) and 0.0 < res_k < 1.0
     keep = False
+    guard = {"res_probe": res_k}
     if warm:
         proj = _projected_sweeps(hist, tol)
+        guard["projected_sweeps"] = proj
         if proj <= maxit - probe:
             rest_mlp = proj * work(info) / max(1, info["outer_sweeps"])
             (slope_d, wps_d), dinfo, xd = default_cost(system, b, probe, **kw)
@@ -261,6 +265,9 @@ def solve_auto(system, A, b, predictor, tol=1e-10, probe=32, **kw):
                 guard_s += dinfo["seconds"]
             rest_def = (math.log(tol) - math.log(res_k)) / slope_d * wps_d if slope_d else math.inf
             keep = rest_mlp <= rest_def
+            guard.update({"rest_work_mlp": rest_mlp, "rest_work_default": rest_def, "slope_mlp": _log_rate(hist),
+                          "slope_default": slope_d, "work_per_sweep_mlp": work(info) / max(1, info["outer_sweeps"]),
+                          "work_per_sweep_default": wps_d})
     if keep:
         x, info = system.solve(b, a, w, tol=tol / res_k, x0=x, maxit_outer=maxit - probe, **kw)
         add(info)
