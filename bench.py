@@ -280,6 +280,9 @@ def measure_sub(workload, args, pred):
     g = gadi.System(A)
     bd = torch.from_numpy(b).cuda()
     eps = args.eps_inner
+    if pred is not None:
+        from paper_2501_04229_amd import predictor as pr
+        pr.default_work(g, bd, tol=1e-10, prec=args.prec, eps_inner=eps)  # the guard's judge, untimed
     for _ in range(max(1, args.warmup)):
         solve_step(g, A, bd, pred, args.prec, eps)
     step_s, infos, x = timed_solves(g, A, bd, pred, args.prec, eps, args.steps)
@@ -321,7 +324,7 @@ def learned_gain(pred, count=8, seed=5, nmin=64, nmax=96):
         bd = torch.from_numpy(b).cuda()
         g.solve(bd, 0.5, 0.5, tol=1e-10, maxit_outer=3)  # launch-shape tuning
         _, idf = g.solve(bd, 0.5, 0.5, tol=1e-10)
-        _, iau, used = pr.solve_auto(g, A, bd, pred, tol=1e-10)
+        _, iau, used = pr.solve_auto(g, A, bd, pred, tol=1e-10, judge=pr.work(idf))
         rows.append({"n": n, "beta": float(beta), "used": used, "status_default": idf["status_str"],
                      "status_auto": iau["status_str"], "sweeps_default": idf["outer_sweeps"],
                      "sweeps_auto": iau["outer_sweeps"], "seconds_default": idf["seconds"],
@@ -392,6 +395,12 @@ def main():
         psrc = "mlp"
     log(f"workload {args.workload}: N={n} nnz={z} setup {setup_s:.1f}s params {psrc} "
         f"alpha={alpha:.4g} omega={omega:.4g}")
+    judge = None
+    if pred is not None:
+        # the guard's judge: the work of a default-parameter solve, measured once per handle (untimed)
+        jw, jinfo = pr.default_work(g, bd, tol=1e-10, prec=args.prec, eps_inner=eps)
+        judge = {"work": jw, "seconds": jinfo["seconds"] if jinfo else None}
+        log(f"judge: default solve {jw:.0f} phases")
     for _ in range(args.warmup):
         x, info, nl, used = solve_step(g, A, bd, pred, args.prec, eps)
         log(f"warmup: {info['status_str']} used={used} sweeps={info['outer_sweeps']} inner_H={info['inner_H']} "
@@ -523,6 +532,8 @@ def main():
                   "barrier_seconds_block0": info["barrier_seconds"]},
         "at_parity_tol": par,
         "default_params_same_prec": default_same,
+        "guard_judge": judge,
+        "guard_last_step": info.get("guard"),
         "fp64_gadi": fp64,
         "speedup_vs_fp64_gadi": speed,
         "spmv": sp,

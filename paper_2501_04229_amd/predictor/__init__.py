@@ -22,9 +22,8 @@ correction and the size dependence of alpha comes from the closed-form
 spectrum; libgadi applies alpha = alpha_ref 10^y0 at prediction time.
 
 The default parameters (0.5, 0.5) are both the fallback and the judge:
-`solve_auto` runs the prediction for a few sweeps and replaces it by the
-default if that run fails, or if at its measured contraction rate it would
-need more work to reach the tolerance than the default would.
+`solve_auto` replaces a prediction by the default if its first sweeps fail, or
+once it has spent the work a default solve needs without converging.
 """
 from __future__ import annotations
 
@@ -196,40 +195,51 @@ def _projected_sweeps(hist, tol):
     return max(0.0, (math.log(tol) - math.log(h[-1])) / slope)
 
 
-def default_cost(system, b, probe=32, **kw):
-    """(log contraction per sweep, work per sweep) of the default parameters on
-    this system, measured once per handle, precision and inner tolerance by a
-    `probe`-sweep run from x = 0 and cached on the handle.  Returns (estimate,
-    probe info or None when the cached value was used, probe iterate)."""
-    key = (kw.get("prec", "fp16"), kw.get("eps_inner"))
-    cache = system.__dict__.setdefault("_default_cost", {})
+def default_work(system, b, tol=1e-10, **kw):
+    """Work (phases) of a default-parameter solve to `tol` from x = 0 on this
+    system -- the judge of a prediction -- measured by one full solve and cached
+    on the handle per precision, inner tolerance and tol.  Returns (work, info
+    of that solve, or None when the cached value was used); work is infinite if
+    the default does not converge."""
+    cache = system.__dict__.setdefault("_default_work", {})
+    key = (kw.get("prec", "fp16"), kw.get("eps_inner"), float(tol))
     if key in cache:
-        return cache[key], None, None
-    x, info = system.solve(b, DEFAULT[0], DEFAULT[1], tol=0.0, maxit_outer=probe, history=True, **kw)
-    slope = _log_rate(system.history) if info["status"] in (gadi.OK, gadi.EMAXIT) else None
-    est = (slope, work(info) / max(1, info["outer_sweeps"]))
-    cache[key] = est
-    return est, info, x
+        return cache[key], None
+    _, info = system.solve(b, DEFAULT[0], DEFAULT[1], tol=tol, **kw)
+    cache[key] = work(info) if info["status"] == gadi.OK else math.inf
+    return cache[key], info
 
 
-def solve_auto(system, A, b, predictor, tol=1e-10, probe=32, **kw):
-    """Solve with the predicted (alpha, omega), guarded by the default (0.5, 0.5).
+def _remember_default_work(system, tol, info, **kw):
+    if info["status"] == gadi.OK:
+        cache = system.__dict__.setdefault("_default_work", {})
+        cache[(kw.get("prec", "fp16"), kw.get("eps_inner"), float(tol))] = work(info)
 
-    The prediction runs `probe` sweeps first.  It is kept only if that run
-    neither fails (half-precision overflow, divergence, breakdown) nor, at its
-    fitted contraction rate, needs more work (phases of the solve kernel) to go
-    from its current residual to `tol` than the default parameters would need
-    for the same reduction at their own rate (`default_cost`, measured on the
-    first call for a handle and cached).  A kept prediction continues from its
-    own iterate; otherwise the default continues from that iterate (or from
-    x = 0 after a failed probe).  Returns (x, info, used) with used in {'mlp',
-    'default'}; info sums sweeps, inner steps and device seconds over every
-    launch of the solve (the default's probe, when it runs, is counted in
-    info['guard_seconds']), and info['fell_back'] = 1 when the default was used."""
+
+def solve_auto(system, A, b, predictor, tol=1e-10, probe=32, judge=None, **kw):
+    """Solve with the predicted (alpha, omega); the default (0.5, 0.5) is the
+    fallback and the judge.
+
+    The judge is the work (phases of the solve kernel) a default solve to `tol`
+    needs on this system: `judge` if given as a number, else the handle's cached
+    value (from `default_work`, or from an earlier default solve from x = 0 in
+    this function), else, with judge='measure', one default solve run first
+    (its device time is reported in info['guard_seconds']).  The prediction
+    runs `probe` sweeps; if that run fails (half-precision overflow,
+    divergence, breakdown), the default solves from x = 0.  Otherwise the
+    prediction continues from its iterate, but may spend at most the judge's
+    work in total: a prediction that has not converged by then needs more work
+    than the default and is rejected -- the default continues from its iterate.
+    Without a judge the prediction continues unless its fitted contraction rate
+    cannot reach `tol` within the sweep limit.  Returns (x, info, used) with
+    used in {'mlp', 'default'}; info sums sweeps, inner steps and device seconds
+    over the launches of the solve, info['fell_back'] = 1 when the default was
+    used, and info['guard'] records the judge and the budget."""
     a, w = predict(predictor, system, A)
     maxit = kw.pop("maxit_outer", 20000)
     probe = min(probe, maxit)
     total = {"outer_sweeps": 0, "inner_H": 0, "inner_S": 0, "seconds": 0.0, "launches": 0}
+    guard = {}
     guard_s = 0.0
 
     def add(info):
@@ -245,7 +255,18 @@ def solve_auto(system, A, b, predictor, tol=1e-10, probe=32, **kw):
         info["guard"] = guard
         return info
 
-    guard = {}
+    if judge is None or judge == "measure":
+        cache = system.__dict__.get("_default_work", {})
+        key = (kw.get("prec", "fp16"), kw.get("eps_inner"), float(tol))
+        if key in cache:
+            judge = cache[key]
+        elif judge == "measure":
+            judge, dinfo = default_work(system, b, tol=tol, maxit_outer=maxit, **kw)
+            guard_s += dinfo["seconds"]
+        else:
+            judge = None
+    guard["judge_work"] = judge
+
     x, info = system.solve(b, a, w, tol=tol, maxit_outer=probe, history=True, **kw)
     add(info)
     if info["status"] == gadi.OK:
@@ -253,30 +274,32 @@ def solve_auto(system, A, b, predictor, tol=1e-10, probe=32, **kw):
     hist = system.history if system.history is not None else np.zeros(0)
     res_k = float(hist[-1]) if len(hist) else 1.0
     warm = info["status"] == gadi.EMAXIT and np.all(np.isfinite(hist)) and 0.0 < res_k < 1.0
-    keep = False
-    guard = {"res_probe": res_k}
     if warm:
-        proj = _projected_sweeps(hist, tol)
-        guard["projected_sweeps"] = proj
-        if proj <= maxit - probe:
-            rest_mlp = proj * work(info) / max(1, info["outer_sweeps"])
-            (slope_d, wps_d), dinfo, xd = default_cost(system, b, probe, **kw)
-            if dinfo is not None:
-                guard_s += dinfo["seconds"]
-            rest_def = (math.log(tol) - math.log(res_k)) / slope_d * wps_d if slope_d else math.inf
-            keep = rest_mlp <= rest_def
-            guard.update({"rest_work_mlp": rest_mlp, "rest_work_default": rest_def, "slope_mlp": _log_rate(hist),
-                          "slope_default": slope_d, "work_per_sweep_mlp": work(info) / max(1, info["outer_sweeps"]),
-                          "work_per_sweep_default": wps_d})
-    if keep:
-        x, info = system.solve(b, a, w, tol=tol / res_k, x0=x, maxit_outer=maxit - probe, **kw)
-        add(info)
-        return x, finish(info, "mlp", res_k), "mlp"
+        spent = work(info)
+        per_sweep = spent / max(1, info["outer_sweeps"])
+        if judge is not None:
+            budget = int(max(0.0, judge - spent) // per_sweep) if math.isfinite(judge) else maxit - probe
+            guard["budget_sweeps"] = budget
+        else:
+            budget = maxit - probe if _projected_sweeps(hist, tol) <= maxit - probe else 0
+            guard["projected_sweeps"] = _projected_sweeps(hist, tol)
+        budget = min(budget, maxit - probe)
+        if budget > 0:
+            x, info = system.solve(b, a, w, tol=tol / res_k, x0=x, maxit_outer=budget, **kw)
+            add(info)
+            if info["status"] == gadi.OK:
+                return x, finish(info, "mlp", res_k), "mlp"
+            if info["status"] == gadi.EMAXIT and np.all(np.isfinite(info["relres"])):
+                res_k *= info["relres"]
+            else:
+                warm = False
     if warm:
-        # the default continues from the prediction's iterate (a valid GADI start)
-        x, info = system.solve(b, DEFAULT[0], DEFAULT[1], tol=tol / res_k, x0=x, maxit_outer=maxit, **kw)
+        # over budget: the default continues from the prediction's iterate (a valid GADI start)
+        x, info = system.solve(b, DEFAULT[0], DEFAULT[1], tol=tol / res_k, x0=x,
+                               maxit_outer=max(1, maxit - total["outer_sweeps"]), **kw)
         add(info)
         return x, finish(info, "default", res_k), "default"
     x, info = system.solve(b, DEFAULT[0], DEFAULT[1], tol=tol, maxit_outer=maxit, **kw)
     add(info)
+    _remember_default_work(system, tol, info, **kw)
     return x, finish(info, "default"), "default"

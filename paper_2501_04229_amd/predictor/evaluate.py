@@ -45,7 +45,7 @@ def evaluate(predictor, count=40, nmin=96, nmax=192, tol=1e-10, maxit_outer=2000
         a, w = pr.predict(predictor, g, A)
         xd, idf = g.solve(b, pr.DEFAULT[0], pr.DEFAULT[1], tol=tol, maxit_outer=maxit_outer)
         xm, iml = g.solve(b, a, w, tol=tol, maxit_outer=maxit_outer)
-        xa, iau, used = pr.solve_auto(g, A, b, predictor, tol=tol, maxit_outer=maxit_outer)
+        xa, iau, used = pr.solve_auto(g, A, b, predictor, tol=tol, maxit_outer=maxit_outer, judge=pr.work(idf))
         ok_m = used == "mlp"
         fb_seconds = iau["seconds"]
         row = {"n": n, "beta": beta, "alpha": a, "omega": w,

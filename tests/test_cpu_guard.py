@@ -64,27 +64,41 @@ def test_faster_prediction_is_kept():
     assert used == "mlp" and info["status"] == gadi.OK and info["fell_back"] == 0
 
 
-def test_slower_prediction_is_rejected_and_the_default_continues_warm():
+def test_prediction_over_the_judges_budget_is_rejected_and_the_default_continues_warm():
+    """The default needs 219 sweeps x 20 phases; the prediction (rate 0.97) may spend that much,
+    has not converged by then, and the default finishes from its iterate."""
     s = FakeSystem({(5.0, 0.5): 0.97, (0.5, 0.5): 0.90}, {(5.0, 0.5): 20, (0.5, 0.5): 20})
-    x, info, used = pr.solve_auto(s, A, None, ConstPredictor(5.0, 0.5), tol=1e-10)
+    x, info, used = pr.solve_auto(s, A, None, ConstPredictor(5.0, 0.5), tol=1e-10, judge="measure")
     assert used == "default" and info["fell_back"] == 1 and info["status"] == gadi.OK
-    # probe of the prediction, probe of the default (cached afterwards), the default warm-started
-    assert [c[0] for c in s.calls] == [(5.0, 0.5), (0.5, 0.5), (0.5, 0.5)] and s.calls[-1][2]
+    assert info["guard"]["judge_work"] == 219 * 20 and info["guard"]["budget_sweeps"] == 219 - 32
+    # the judge's solve, the probe, the continuation up to the budget, the default from the iterate
+    assert [c[0] for c in s.calls] == [(0.5, 0.5), (5.0, 0.5), (5.0, 0.5), (0.5, 0.5)]
+    assert s.calls[2][1] == 219 - 32 and s.calls[3][2]
     assert info["guard_seconds"] > 0
+    # the judge is cached on the handle: no second default solve, no guard time
     s.calls.clear()
-    pr.solve_auto(s, A, None, ConstPredictor(5.0, 0.5), tol=1e-10)
-    assert [c[0] for c in s.calls] == [(5.0, 0.5), (0.5, 0.5)]
+    x, info, used = pr.solve_auto(s, A, None, ConstPredictor(5.0, 0.5), tol=1e-10, judge="measure")
+    assert [c[0] for c in s.calls] == [(5.0, 0.5), (5.0, 0.5), (0.5, 0.5)] and info["guard_seconds"] == 0.0
 
 
 def test_cheaper_per_sweep_prediction_is_kept_despite_more_sweeps():
-    """Work, not sweeps, decides: more sweeps at a third of the work per sweep win."""
+    """Work, not sweeps, decides: more sweeps at a third of the work per sweep fit the budget."""
     s = FakeSystem({(0.3, 0.5): 0.92, (0.5, 0.5): 0.90}, {(0.3, 0.5): 10, (0.5, 0.5): 30})
-    x, info, used = pr.solve_auto(s, A, None, ConstPredictor(0.3, 0.5), tol=1e-10)
-    assert used == "mlp"
+    x, info, used = pr.solve_auto(s, A, None, ConstPredictor(0.3, 0.5), tol=1e-10, judge=219 * 30)
+    assert used == "mlp" and info["status"] == gadi.OK
 
 
-def test_failed_prediction_restarts_the_default_from_zero():
+def test_failed_prediction_restarts_the_default_from_zero_and_caches_the_judge():
     s = FakeSystem({(0.5, 0.5): 0.9}, {(0.5, 0.5): 20}, fail=[(1e-3, 0.5)])
     x, info, used = pr.solve_auto(s, A, None, ConstPredictor(1e-3, 0.5), tol=1e-10)
     assert used == "default" and info["status"] == gadi.OK
     assert s.calls[-1] == ((0.5, 0.5), 20000, False)
+    assert list(s._default_work.values()) == [219 * 20]
+
+
+def test_without_a_judge_a_stalled_prediction_is_replaced():
+    """No cached judge: a probe whose fitted rate cannot reach tol within the sweep limit hands
+    over to the default."""
+    s = FakeSystem({(7.0, 0.5): 0.9995, (0.5, 0.5): 0.9}, {(7.0, 0.5): 20, (0.5, 0.5): 20})
+    x, info, used = pr.solve_auto(s, A, None, ConstPredictor(7.0, 0.5), tol=1e-10, maxit_outer=5000)
+    assert used == "default" and info["status"] == gadi.OK

@@ -33,7 +33,8 @@ def gain_records(p, subset=SUBSET, tol=1e-10):
         bd = torch.from_numpy(b).cuda()
         g.solve(bd, 0.5, 0.5, tol=tol, maxit_outer=3)  # launch-shape tuning, not timed
         xd, idf = g.solve(bd, 0.5, 0.5, tol=tol)
-        xa, iau, used = pr.solve_auto(g, A, bd, p, tol=tol)
+        # the default's measured work is the judge of the prediction
+        xa, iau, used = pr.solve_auto(g, A, bd, p, tol=tol, judge=pr.work(idf))
         torch.cuda.synchronize()
         rows.append({"n": n, "beta": beta, "A": A, "b": b, "x": xa.cpu().numpy(), "used": used,
                      "default": idf, "auto": iau,
