@@ -420,6 +420,19 @@ def main():
         q = lambda v: {"min": float(np.min(v)), "median": float(np.median(v)), "max": float(np.max(v)),
                        "argmin": int(np.argmin(v)), "argmax": int(np.argmax(v))}
         blocks = {"compute_seconds": q(comp), "barrier_seconds": q(bw), "launch_seconds": float(np.max(bt))}
+        ph, pid = g.phase_block_profile()
+        if len(ph):
+            # per phase: the slowest block against the median block
+            lag = ph.max(axis=1) - np.median(ph, axis=1)
+            slow = ph.argmax(axis=1)
+            blocks["phases_recorded"] = int(len(ph))
+            blocks["phase_lag_seconds_mean"] = float(lag.mean())
+            blocks["phase_median_seconds_mean"] = float(np.median(ph, axis=1).mean())
+            blocks["slowest_block_repeats"] = float(np.mean(slow[1:] == slow[:-1]))
+            blocks["slowest_blocks_top"] = np.bincount(slow, minlength=ph.shape[1]).argsort()[::-1][:8].tolist()
+            log(f"per-phase lag of the slowest block: mean {lag.mean() * 1e6:.1f} us over "
+                f"{len(ph)} phases (median phase {np.median(ph, axis=1).mean() * 1e6:.1f} us); "
+                f"top slow blocks {blocks['slowest_blocks_top']}")
         log(f"per-block compute s (last launch): min {np.min(comp):.4f} median {np.median(comp):.4f} "
             f"max {np.max(comp):.4f}; in barriers: min {np.min(bw):.4f} max {np.max(bw):.4f}")
     xh = x.cpu().numpy()

@@ -164,6 +164,13 @@ gadi_status gadi_ir_solve_noalloc(gadi_handle* h, const double* b, double* x, do
  * may be NULL).  Returns the number of blocks filled (0 if none). */
 int32_t gadi_get_block_profile(gadi_handle* h, double* wait_seconds, double* total_seconds, int32_t cap);
 
+/* Per-block timing of each of the first 96 phases (the compute between two
+ * device-wide barriers) of the last gadi_ir_solve launch: seconds[p * blocks +
+ * b] for phase p and block b (blocks = gadi_solver_blocks), ids[p] the phase
+ * kind (the order of gadi_get_phase_profile).  Host arrays for up to
+ * max_phases phases; returns the number of phases filled. */
+int32_t gadi_get_phase_block_profile(gadi_handle* h, double* seconds, int32_t* ids, int32_t max_phases);
+
 /* RES history of the last solve with record_history = 1: copies up to `cap`
  * values (RES before each sweep) into `out` (host) and returns the count. */
 int32_t gadi_get_history(gadi_handle* h, double* out, int32_t cap);

@@ -78,6 +78,7 @@ def _load():
         "gadi_get_layout": (i32, [vp, P(i64)]),
         "gadi_get_phase_profile": (i32, [vp, P(f64), P(i64)]),
         "gadi_get_block_profile": (i32, [vp, P(f64), P(f64), i32]),
+        "gadi_get_phase_block_profile": (i32, [vp, P(f64), P(i32), i32]),
         "gadi_features": (i32, [vp, i32, i32, P(f64), P(ctypes.c_float)]),
         "gadi_mlp_create": (i32, [ctypes.c_uint64, P(vp)]),
         "gadi_mlp_destroy": (i32, [vp]),
@@ -310,6 +311,15 @@ class System:
         k = _lib.gadi_get_block_profile(self._h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                         t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 4096)
         return w[:k], t[:k]
+
+    def phase_block_profile(self, max_phases=96):
+        """(seconds [phases, blocks], phase ids [phases]) of the first phases of the last solve launch."""
+        nb, _ = self.solver_blocks()
+        sec = np.zeros(max_phases * max(nb, 1))
+        ids = np.zeros(max_phases, np.int32)
+        k = _lib.gadi_get_phase_block_profile(self._h, sec.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                              ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), max_phases)
+        return sec[:k * nb].reshape(k, nb), ids[:k]
 
     def layout(self):
         """Packed layout counts: dict with n, npad, nnz_off, slots, dia_slots,

@@ -258,11 +258,157 @@ struct Grid {
   unsigned long long epoch;
   long long timeout;
   long long wait_ticks;  // thread 0: wall-clock ticks this block spent inside barriers
+  // XCC-hierarchical variant (kind 1): this block's XCC, the XCC's block
+  // count and (block 0) the XCCs in use
+  int kind = 0;
+  unsigned xcc = 0, xcc_n = 0, xcc_mask = 0;
+  unsigned long long h0 = 0;  // epoch at which the hierarchical barrier took over
 };
+
+// Per-XCC line k (0 block count, 1 arrivals, 2 arrival epoch) of XCC x.
+__device__ __forceinline__ unsigned long long* xcc_line(unsigned long long* flags, int k, unsigned x) {
+  return flags + (size_t)(kMaxBlocks + k * kMaxXcc + (int)x) * kFlagStride;
+}
+
+// The XCC (L2 domain) that runs the calling wave.
+__device__ __forceinline__ unsigned current_xcc() {
+  return (unsigned)__builtin_amdgcn_s_getreg((3 << 11) | 20) & 0xFu;  // HW_REG_XCC_ID, bits [3:0]
+}
+
+// Waits until this wave's outstanding vector memory operations, stores
+// included, have completed (s_waitcnt vmcnt(0)).
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 struct Red4 {
   double v[4];
 };
+
+// XCC-hierarchical all-reduce.  A block that arrives has its phase stores in
+// its XCC's L2 (every wave waited for them); it publishes its partials and
+// counts itself in its XCC's arrival counter.  The XCC's last arriver writes
+// the L2 back once for all of the XCC's blocks (one agent-scope release per
+// XCC instead of one per block) and publishes the XCC's epoch.  Block 0 waits
+// for every XCC in use, combines the partials in block order and releases the
+// grid through one word; every block takes its own agent-scope acquire after
+// it sees that word.  Timeouts set the abort flag as in the relay barrier.
+template <int BLOCK>
+static __device__ __forceinline__ Red4 xcc_allreduce(Grid& g, double (*sh)[4], int& sh_abort, long long t_enter,
+                                                  bool& ok) {
+  constexpr int NW = BLOCK / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  g.epoch += 1;
+  const unsigned parity = (unsigned)(g.epoch & 1ull);
+  if (tid == 0) {
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      t0 += sh[w][0];
+      t1 += sh[w][1];
+      t2 += sh[w][2];
+      t3 = fmax(t3, sh[w][3]);
+    }
+    double* p = g.part + ((size_t)parity * kMaxBlocks + blockIdx.x) * 4;
+    p[0] = t0;
+    p[1] = t1;
+    p[2] = t2;
+    p[3] = t3;
+    sh_abort = 0;
+    wait_vmem();  // the partials are in the L2
+    const unsigned long long target = (g.epoch - g.h0) * (unsigned long long)g.xcc_n;
+    const unsigned long long before =
+        __hip_atomic_fetch_add(xcc_line(g.flags, 1, g.xcc), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (before + 1 == target) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(xcc_line(g.flags, 2, g.xcc), g.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  if (blockIdx.x == 0) {
+    const long long t_start = wall_clock64();
+    for (;;) {
+      int mine = 1;
+      if (tid < kMaxXcc && ((g.xcc_mask >> tid) & 1u))
+        mine = __hip_atomic_load(xcc_line(g.flags, 2, (unsigned)tid), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+               g.epoch;
+      if (__syncthreads_and(mine)) break;
+      const int expired = (tid == 0) && (wall_clock64() - t_start > g.timeout ||
+                                         __hip_atomic_load(&g.sync->abort, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT) != 0);
+      if (__syncthreads_or(expired)) {
+        if (tid == 0) {
+          __hip_atomic_store(&g.sync->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          sh_abort = 1;
+        }
+        break;
+      }
+    }
+    if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      wait_vmem();
+    }
+    __syncthreads();
+    double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+    for (unsigned k = tid; k < g.nblocks; k += BLOCK) {
+      const double* p = g.part + ((size_t)parity * kMaxBlocks + k) * 4;
+      b0 += p[0];
+      b1 += p[1];
+      b2 += p[2];
+      b3 = fmax(b3, p[3]);
+    }
+    b0 = wave_sum(b0);
+    b1 = wave_sum(b1);
+    b2 = wave_sum(b2);
+    b3 = wave_max(b3);
+    __syncthreads();
+    if (lane == 0) {
+      sh[wid][0] = b0;
+      sh[wid][1] = b1;
+      sh[wid][2] = b2;
+      sh[wid][3] = b3;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+      for (int w = 0; w < NW; ++w) {
+        r0 += sh[w][0];
+        r1 += sh[w][1];
+        r2 += sh[w][2];
+        r3 = fmax(r3, sh[w][3]);
+      }
+      double* r = g.result + parity * 4;
+      r[0] = r0;
+      r[1] = r1;
+      r[2] = r2;
+      r[3] = r3;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&g.sync->release, g.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if (tid == 0) {
+    const long long t_start = wall_clock64();
+    unsigned spins = 0;
+    while (__hip_atomic_load(&g.sync->release, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < g.epoch) {
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 255u) == 0u) {
+        if (__hip_atomic_load(&g.sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+            wall_clock64() - t_start > g.timeout) {
+          __hip_atomic_store(&g.sync->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          sh_abort = 1;
+          break;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  Red4 out;
+  const double* r = g.result + parity * 4;
+  out.v[0] = r[0];
+  out.v[1] = r[1];
+  out.v[2] = r[2];
+  out.v[3] = r[3];
+  ok = sh_abort == 0;
+  if (tid == 0) g.wait_ticks += wall_clock64() - t_enter;
+  __syncthreads();  // shared state is rewritten by the next call
+  return out;
+}
 
 template <int BLOCK>
 static __device__ __forceinline__ Red4 grid_allreduce(Grid& g, double s0, double s1, double s2, double m3,
@@ -280,6 +426,11 @@ static __device__ __forceinline__ Red4 grid_allreduce(Grid& g, double s0, double
       sh[wid][2] = a2;
       sh[wid][3] = a3;
     }
+  }
+  if (g.kind == 1) {
+    wait_vmem();  // this wave's phase stores are in the L2 before the block arrives
+    __syncthreads();
+    return xcc_allreduce<BLOCK>(g, sh, sh_abort, t_enter, ok);
   }
   __syncthreads();
   g.epoch += 1;

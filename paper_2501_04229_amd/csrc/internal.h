@@ -26,10 +26,22 @@ constexpr int kPadRows = kTile;
 constexpr int kMaxBlocks = 4096;
 // Stride between per-block arrival flags (one 64-byte line each).
 constexpr int kFlagStride = 8;
+// The XCC-hierarchical barrier keeps per-XCC lines after the per-block flags:
+// line kMaxBlocks + k * kMaxXcc + x holds, for XCC x, k = 0 its block count,
+// 1 its arrival count, 2 its arrival epoch.
+constexpr int kMaxXcc = 16;
+constexpr int kFlagWords = (kMaxBlocks + 3 * kMaxXcc) * kFlagStride;
+// barrier of the solve kernel unless GADI_BARRIER says otherwise (0 relay, 1 XCC-hierarchical)
+constexpr int kDefaultBarrier = 1;
 // Per-phase profile of block 0 (ticks [10], counts [10]), then per block the
 // ticks inside barriers [kMaxBlocks] and in the whole launch [kMaxBlocks].
 constexpr int kProfHead = 20;
-constexpr int kProfLen = kProfHead + 2 * 4096;
+// ... then each block's ticks of each of the first kPhaseRec phases
+// [kPhaseRec][kMaxBlocks] and the phases' ids [kPhaseRec].
+constexpr int kPhaseRec = 96;
+constexpr int kProfPhase = kProfHead + 2 * 4096;
+constexpr int kProfPhaseId = kProfPhase + kPhaseRec * 4096;
+constexpr int kProfLen = kProfPhaseId + kPhaseRec;
 // Largest number of distinct column offsets of a diagonal-style slice.
 constexpr int kDiaMax = 8;
 // largest system: its padded double vectors stay below 4 GiB

@@ -13,9 +13,10 @@
 namespace gadi {
 
 gadi_status launch_solve_shape(System& s, int prec, SolveArgs a, int block, int per_cu, bool fused);
+int barrier_kind();
 double wall_clock_hz();
 
-// 1 MiB of barrier / reduction state, then 13 double-sized vectors of the
+// 1 MiB of barrier / reduction state (about 0.53 MiB used), then 13 double-sized vectors of the
 // padded length: the largest padded system is (256 MiB - 1 MiB) / 104 bytes
 // per row = 2,573,753 rows (a 128^3 grid is 2,097,152).
 constexpr size_t kScratchBytes = size_t(256) << 20;
@@ -94,7 +95,7 @@ extern "C" gadi_status gadi_ir_solve_noalloc(gadi_handle* h, const double* b, do
 
   SyncState* sync = (SyncState*)base;
   unsigned long long* flags = (unsigned long long*)(base + 256);
-  double* part = (double*)(flags + (size_t)kMaxBlocks * kFlagStride);
+  double* part = (double*)(flags + (size_t)kFlagWords);
   double* result = part + 2 * kMaxBlocks * 4;
   DevInfo* dinfo = (DevInfo*)(result + 8);
   double* db = (double*)(base + kCtrlBytes);
@@ -139,6 +140,7 @@ extern "C" gadi_status gadi_ir_solve_noalloc(gadi_handle* h, const double* b, do
   a.info = dinfo;
   a.hist = nullptr;
   a.prof = nullptr;
+  a.barrier = barrier_kind();
   if (o.prec == GADI_PREC_FP16_IR) {
     a.h_off = s.h_off16;
     a.s_off = s.s_off16;

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <map>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -44,6 +45,16 @@ long long barrier_timeout_ticks() {
 
 int num_cus() { return g_num_cus; }
 
+// Device-wide barrier of the solve kernel: 1 = XCC-hierarchical (one L2
+// writeback per XCC and phase), 0 = relay through block 0 with every block's
+// own release; GADI_BARRIER=relay|xcc overrides the default.
+int barrier_kind() {
+  const char* e = std::getenv("GADI_BARRIER");
+  if (e && std::string(e) == "relay") return 0;
+  if (e && std::string(e) == "xcc") return 1;
+  return kDefaultBarrier;
+}
+
 gadi_status ensure_workspace(System& s) {
   GADI_HIP_CHECK(hipSetDevice(s.device));
   if (s.ws) return GADI_OK;
@@ -55,7 +66,7 @@ gadi_status ensure_workspace(System& s) {
   GADI_HIP_CHECK(hipMalloc((void**)&s.sync, sizeof(SyncState)));
   GADI_HIP_CHECK(hipMemset(s.sync, 0, sizeof(SyncState)));
   GADI_HIP_CHECK(hipMalloc((void**)&s.part, sizeof(double) * 2 * kMaxBlocks * 4));
-  GADI_HIP_CHECK(hipMalloc((void**)&s.flags, sizeof(unsigned long long) * kMaxBlocks * kFlagStride));
+  GADI_HIP_CHECK(hipMalloc((void**)&s.flags, sizeof(unsigned long long) * kFlagWords));
   GADI_HIP_CHECK(hipMalloc((void**)&s.result, sizeof(double) * 8));
   GADI_HIP_CHECK(hipMalloc((void**)&s.info, sizeof(DevInfo)));
   GADI_HIP_CHECK(hipMalloc((void**)&s.prof, sizeof(long long) * kProfLen));
@@ -363,6 +374,7 @@ extern "C" gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x,
   a.hist = o.record_history ? s.hist : nullptr;
   a.timeout = barrier_timeout_ticks();
   a.prof = s.prof;
+  a.barrier = barrier_kind();
   if (o.prec == GADI_PREC_FP16_IR || o.prec == GADI_PREC_H_D_S || o.prec == GADI_PREC_H_S_S) {
     a.h_off = s.h_off16;
     a.s_off = s.s_off16;
@@ -461,4 +473,21 @@ extern "C" int32_t gadi_get_block_profile(gadi_handle* h, double* wait_seconds, 
     if (total_seconds) total_seconds[i] = (double)buf[kMaxBlocks + i] / hz;
   }
   return nb;
+}
+
+extern "C" int32_t gadi_get_phase_block_profile(gadi_handle* h, double* seconds, int32_t* ids, int32_t max_phases) {
+  if (!h || !h->sys.prof || h->sys.last_blocks <= 0 || max_phases <= 0) return 0;
+  const int nb = h->sys.last_blocks;
+  const int np = max_phases < kPhaseRec ? max_phases : kPhaseRec;
+  std::vector<long long> buf((size_t)kPhaseRec * kMaxBlocks + kPhaseRec);
+  if (hipMemcpy(buf.data(), h->sys.prof + kProfPhase, sizeof(long long) * buf.size(), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return 0;
+  const double hz = (double)g_wall_rate_khz * 1000.0;
+  for (int p = 0; p < np; ++p) {
+    if (ids) ids[p] = (int32_t)buf[(size_t)kPhaseRec * kMaxBlocks + p];
+    if (seconds)
+      for (int b = 0; b < nb; ++b) seconds[(size_t)p * nb + b] = (double)buf[(size_t)p * kMaxBlocks + b] / hz;
+  }
+  return np;
 }

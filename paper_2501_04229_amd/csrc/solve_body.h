@@ -61,6 +61,7 @@ struct SolveArgs {
   unsigned long long* prune;
   // optional per-phase profile of block 0: wall-clock ticks [10], phase counts [10]
   long long* prof;
+  int barrier;  // device-wide barrier: 0 relay, 1 XCC-hierarchical
 };
 
 // Reduction into out[4] under the caller's synchronisation policy; leaves the
@@ -137,15 +138,24 @@ struct BlockRed {
 
 // The same, charging the block-0 time since the previous reduction to phase
 // `id` of the optional per-phase profile (a.prof: ticks[10], counts[10]).
-#define ALLREDUCE_P(id, a0, a1, a2, a3)                                    \
-  do {                                                                     \
-    if (a.prof && blockIdx.x == 0 && threadIdx.x == 0) {                   \
-      const long long now_ = wall_clock64();                               \
-      a.prof[(id)] += now_ - t_mark;                                       \
-      a.prof[10 + (id)] += 1;                                              \
-    }                                                                      \
-    ALLREDUCE(a0, a1, a2, a3);                                             \
-    if (a.prof && blockIdx.x == 0 && threadIdx.x == 0) t_mark = wall_clock64(); \
+// Every block also records its time of each of the first kPhaseRec phases
+// (load-balance diagnostics), and block 0 the phase ids.
+#define ALLREDUCE_P(id, a0, a1, a2, a3)                                        \
+  do {                                                                         \
+    if (a.prof && threadIdx.x == 0) {                                          \
+      const long long now_ = wall_clock64();                                   \
+      if (blockIdx.x == 0) {                                                   \
+        a.prof[(id)] += now_ - t_mark;                                         \
+        a.prof[10 + (id)] += 1;                                                \
+      }                                                                        \
+      if (nphase < kPhaseRec) {                                                \
+        a.prof[kProfPhase + (size_t)nphase * kMaxBlocks + blockIdx.x] = now_ - t_mark; \
+        if (blockIdx.x == 0) a.prof[kProfPhaseId + nphase] = (id);             \
+      }                                                                        \
+      ++nphase;                                                                \
+    }                                                                          \
+    ALLREDUCE(a0, a1, a2, a3);                                                 \
+    if (a.prof && threadIdx.x == 0) t_mark = wall_clock64();                   \
   } while (0)
 
 static __device__ __forceinline__ int clamp_exp(int e) { return e < -120 ? -120 : (e > 120 ? 120 : e); }
@@ -346,7 +356,8 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
   auto ldv = [](VT v) { return ld<AT>(v); };
 
   double out[4];
-  long long t_mark = (a.prof && blockIdx.x == 0 && threadIdx.x == 0) ? wall_clock64() : 0;
+  long long t_mark = (a.prof && threadIdx.x == 0) ? wall_clock64() : 0;
+  int nphase = 0;
   double rho0 = 0.0, res = 0.0;
   int status = GADI_EMAXIT;
   int sweep = 0;

@@ -16,6 +16,34 @@ template <class Mode, int BLOCK, bool FUSED, int PW>
 __global__ void __launch_bounds__(BLOCK) solve_kernel(SolveArgs a) {
   const long long t_begin = wall_clock64();
   GridRed<BLOCK> red{Grid{a.sync, a.flags, a.part, a.result, gridDim.x, 0ull, a.timeout, 0ll}};
+  if (a.barrier == 1) {
+    // XCC-hierarchical barrier: every block counts itself in the XCC that runs
+    // it; after one relay barrier every block knows its XCC's block count and
+    // block 0 the XCCs in use
+    __shared__ unsigned sh_x[3];
+    if (threadIdx.x == 0) {
+      const unsigned x = current_xcc();
+      __hip_atomic_fetch_add(xcc_line(a.flags, 0, x), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      sh_x[0] = x;
+    }
+    bool ok0;
+    (void)red.reduce(0.0, 0.0, 0.0, 0.0, ok0);
+    if (!ok0) return;
+    if (threadIdx.x == 0) {
+      unsigned mask = 0;
+      for (unsigned i = 0; i < (unsigned)kMaxXcc; ++i)
+        if (__hip_atomic_load(xcc_line(a.flags, 0, i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0) mask |= 1u << i;
+      sh_x[1] = (unsigned)__hip_atomic_load(xcc_line(a.flags, 0, sh_x[0]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      sh_x[2] = mask;
+    }
+    __syncthreads();
+    red.g.kind = 1;
+    red.g.xcc = sh_x[0];
+    red.g.xcc_n = sh_x[1];
+    red.g.xcc_mask = sh_x[2];
+    red.g.h0 = red.g.epoch;  // arrivals are counted from here
+    __syncthreads();
+  }
   const unsigned lb = logical_block(blockIdx.x, gridDim.x);
   const int t0 = (int)((long long)a.ntiles * lb / gridDim.x);
   const int t1 = (int)((long long)a.ntiles * (lb + 1) / gridDim.x);
@@ -46,7 +74,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(SolveArgs a) {
 }
 
 static __global__ void reset_sync_kernel(SyncState* s, unsigned long long* flags, DevInfo* info, long long* prof) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kMaxBlocks * kFlagStride; i += gridDim.x * blockDim.x)
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kFlagWords; i += gridDim.x * blockDim.x)
     flags[i] = 0ull;
   if (prof && blockIdx.x == 0 && threadIdx.x < 20) prof[threadIdx.x] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
