@@ -444,11 +444,12 @@ def main():
     achieved = sm["algorithmic_bytes"] / sm["kernel_seconds"] / 1e9
     moved = sm["moved_bytes"] / sm["kernel_seconds"] / 1e9
     nb, thr = g.solver_blocks()
+    form = g.solver_form()
     log(f"{args.prec}-IR: {step_s:.4f}s/solve, kernel {sm['kernel_seconds'] / args.steps:.4f}s, "
         f"{achieved:.0f} GB/s algorithmic, {moved:.0f} GB/s moved, sweeps={info['outer_sweeps']} "
         f"inner_H={info['inner_H']} inner_S={info['inner_S']} relres={info['relres']:.3e} "
         f"err_vs_x*={rel_err_xstar:.3e} barriers={info['barriers']} "
-        f"block0 in barriers {info['barrier_seconds']:.3f}s, launch {nb} x {thr}")
+        f"block0 in barriers {info['barrier_seconds']:.3f}s, launch {nb} x {thr}, inner form {form}")
 
     # the outer tolerance that makes the 1e-8 match with the oracle provable
     par = None
@@ -536,7 +537,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "N": n, "nnz": z, "tol": 1e-10, "eps_inner": eps_used,
                    "alpha_predicted": alpha, "omega_predicted": omega, "params": psrc, "used": used,
-                   "prec": args.prec, "solve_launch_blocks_threads": [nb, thr],
+                   "prec": args.prec, "solve_launch_blocks_threads": [nb, thr], "inner_form": form,
+                   "barrier": os.environ.get("GADI_BARRIER", "library default"),
                    "tiles_per_block": lay["npad"] / thr / nb},
         "layout": lay,
         "solve": {"status": info["status_str"], "sweeps": info["outer_sweeps"], "inner_H": info["inner_H"],

@@ -290,8 +290,17 @@ gadi_status gadi_get_layout(gadi_handle* h, int64_t* out);
  * blocks and stores the threads per block in *threads (may be NULL); 0 before
  * the first solve.  The shape is chosen per handle and precision by a timed
  * trial of candidate shapes on the first solve (override with the environment
- * variables GADI_SOLVE_BLOCK and GADI_BLOCKS_PER_CU). */
+ * variables GADI_SOLVE_BLOCK, GADI_BLOCKS_PER_CU and GADI_SOLVE_FORM). */
 int32_t gadi_solver_blocks(gadi_handle* h, int32_t* threads);
+
+/* Inner-solver form of the last gadi_ir_solve on this handle (-1 before the
+ * first solve): 0 Hestenes-Stiefel CG and CGNE, 1 Chronopoulos-Gear CG and
+ * CGNE (one reduction per step, neighbour values recomputed), 2 pipelined CG
+ * (the product on K w, one phase per step) with Craig's CGNE, 3 Hestenes-Stiefel
+ * CG with Craig's CGNE.  All of them compute
+ * the inner iterations of Algorithm 1; the timed trial picks one per handle and
+ * precision with the launch shape (override: GADI_SOLVE_FORM). */
+int32_t gadi_solver_form(gadi_handle* h);
 
 /* ------------------------------------------------------------------------
  * GADI-AB for the continuous Sylvester equation A X + X B = C (Section 4.3):

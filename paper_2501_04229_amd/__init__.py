@@ -95,6 +95,7 @@ def _load():
         "gadi_destroy": (i32, [vp]),
         "gadi_status_str": (ctypes.c_char_p, [i32]),
         "gadi_solver_blocks": (i32, [vp, P(i32)]),
+        "gadi_solver_form": (i32, [vp]),
         "gadi_default_options": (None, [P(_Options), ctypes.c_int]),
         "gadi_sylv_setup": (i32, [i32, i32, vp, vp, vp, vp, vp, vp, P(vp)]),
         "gadi_sylv_solve": (i32, [vp, vp, vp, f64, f64, f64, P(_Options), P(SolveInfo)]),
@@ -343,6 +344,12 @@ class System:
         t = ctypes.c_int32(0)
         nb = _lib.gadi_solver_blocks(self._h, ctypes.byref(t))
         return int(nb), int(t.value)
+
+    def solver_form(self):
+        """Inner-solver form of the last solve launch (0 Hestenes-Stiefel,
+        1 Chronopoulos-Gear, 2 pipelined CG with Craig's CGNE, 3 Hestenes-Stiefel
+        CG with Craig's CGNE; -1 before any)."""
+        return int(_lib.gadi_solver_form(self._h))
 
 
 def solve_batched(systems, bs, alphas, omegas, tol=1e-10, prec="fp16", eps_inner=None, maxit_outer=5000,

@@ -258,8 +258,8 @@ struct Grid {
   unsigned long long epoch;
   long long timeout;
   long long wait_ticks;  // thread 0: wall-clock ticks this block spent inside barriers
-  // XCC-hierarchical variant (kind 1): this block's XCC, the XCC's block
-  // count and (block 0) the XCCs in use
+  // XCC-hierarchical variants (kind 1, 2): this block's XCC, the XCC's block
+  // count and the XCCs in use
   int kind = 0;
   unsigned xcc = 0, xcc_n = 0, xcc_mask = 0;
   unsigned long long h0 = 0;  // epoch at which the hierarchical barrier took over
@@ -268,6 +268,12 @@ struct Grid {
 // Per-XCC line k (0 block count, 1 arrivals, 2 arrival epoch) of XCC x.
 __device__ __forceinline__ unsigned long long* xcc_line(unsigned long long* flags, int k, unsigned x) {
   return flags + (size_t)(kMaxBlocks + k * kMaxXcc + (int)x) * kFlagStride;
+}
+
+// Word x of the packed arrival epochs (direct variant): one word per XCC in
+// consecutive words, so that one wavefront load reads every XCC's epoch.
+__device__ __forceinline__ unsigned long long* xcc_epoch_word(unsigned long long* flags, unsigned x) {
+  return flags + (size_t)(kMaxBlocks + 3 * kMaxXcc) * kFlagStride + x;
 }
 
 // The XCC (L2 domain) that runs the calling wave.
@@ -410,6 +416,107 @@ static __device__ __forceinline__ Red4 xcc_allreduce(Grid& g, double (*sh)[4], i
   return out;
 }
 
+// XCC-hierarchical all-reduce without a master (kind 2).  Arrival as in
+// xcc_allreduce, except that an XCC's last arriver publishes the XCC's epoch
+// in the packed word array.  Every block then waits for all XCCs in use with
+// one wavefront (a lane per XCC, one load of the packed words per poll), takes
+// its agent-scope acquire and combines the partials itself, in block order
+// with the same code in every block, so every block computes the same bits.
+// This saves the master's relay: its wait, its release of the result and the
+// other blocks' wait for that release.  The partials are double-buffered by
+// epoch parity: a block writes the buffer of epoch e + 2 only after every
+// block has arrived at e + 1, hence finished reading the partials of e.
+template <int BLOCK>
+static __device__ __forceinline__ Red4 xcc_direct_allreduce(Grid& g, double (*sh)[4], int& sh_abort,
+                                                         long long t_enter, bool& ok) {
+  constexpr int NW = BLOCK / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  g.epoch += 1;
+  const unsigned parity = (unsigned)(g.epoch & 1ull);
+  if (tid == 0) {
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      t0 += sh[w][0];
+      t1 += sh[w][1];
+      t2 += sh[w][2];
+      t3 = fmax(t3, sh[w][3]);
+    }
+    double* p = g.part + ((size_t)parity * kMaxBlocks + blockIdx.x) * 4;
+    p[0] = t0;
+    p[1] = t1;
+    p[2] = t2;
+    p[3] = t3;
+    sh_abort = 0;
+    wait_vmem();  // the partials are in the L2
+    const unsigned long long target = (g.epoch - g.h0) * (unsigned long long)g.xcc_n;
+    const unsigned long long before =
+        __hip_atomic_fetch_add(xcc_line(g.flags, 1, g.xcc), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (before + 1 == target) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(xcc_epoch_word(g.flags, g.xcc), g.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  if (wid == 0) {
+    const long long t_start = wall_clock64();
+    const bool watch = lane < kMaxXcc && ((g.xcc_mask >> lane) & 1u);
+    unsigned spins = 0;
+    for (;;) {
+      int mine = 1;
+      if (watch)
+        mine = __hip_atomic_load(xcc_epoch_word(g.flags, (unsigned)lane), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT) >= g.epoch;
+      if (__all(mine)) break;
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 255u) == 0u) {
+        const int expired = wall_clock64() - t_start > g.timeout ||
+                            __hip_atomic_load(&g.sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        if (__any(expired)) {
+          if (lane == 0) {
+            __hip_atomic_store(&g.sync->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sh_abort = 1;
+          }
+          break;
+        }
+      }
+    }
+    if (lane == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+  for (unsigned k = tid; k < g.nblocks; k += BLOCK) {
+    const double* p = g.part + ((size_t)parity * kMaxBlocks + k) * 4;
+    b0 += p[0];
+    b1 += p[1];
+    b2 += p[2];
+    b3 = fmax(b3, p[3]);
+  }
+  b0 = wave_sum(b0);
+  b1 = wave_sum(b1);
+  b2 = wave_sum(b2);
+  b3 = wave_max(b3);
+  // sh (this block's arrival sums) was last read by thread 0 before the barrier above
+  if (lane == 0) {
+    sh[wid][0] = b0;
+    sh[wid][1] = b1;
+    sh[wid][2] = b2;
+    sh[wid][3] = b3;
+  }
+  __syncthreads();
+  Red4 out;
+  out.v[0] = out.v[1] = out.v[2] = out.v[3] = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    out.v[0] += sh[w][0];
+    out.v[1] += sh[w][1];
+    out.v[2] += sh[w][2];
+    out.v[3] = fmax(out.v[3], sh[w][3]);
+  }
+  ok = sh_abort == 0;
+  if (tid == 0) g.wait_ticks += wall_clock64() - t_enter;
+  __syncthreads();  // shared state is rewritten by the next call
+  return out;
+}
+
 template <int BLOCK>
 static __device__ __forceinline__ Red4 grid_allreduce(Grid& g, double s0, double s1, double s2, double m3,
                                                       bool& ok) {
@@ -427,10 +534,11 @@ static __device__ __forceinline__ Red4 grid_allreduce(Grid& g, double s0, double
       sh[wid][3] = a3;
     }
   }
-  if (g.kind == 1) {
+  if (g.kind != 0) {
     wait_vmem();  // this wave's phase stores are in the L2 before the block arrives
     __syncthreads();
-    return xcc_allreduce<BLOCK>(g, sh, sh_abort, t_enter, ok);
+    return g.kind == 2 ? xcc_direct_allreduce<BLOCK>(g, sh, sh_abort, t_enter, ok)
+                       : xcc_allreduce<BLOCK>(g, sh, sh_abort, t_enter, ok);
   }
   __syncthreads();
   g.epoch += 1;

@@ -28,11 +28,13 @@ constexpr int kMaxBlocks = 4096;
 constexpr int kFlagStride = 8;
 // The XCC-hierarchical barrier keeps per-XCC lines after the per-block flags:
 // line kMaxBlocks + k * kMaxXcc + x holds, for XCC x, k = 0 its block count,
-// 1 its arrival count, 2 its arrival epoch.
+// 1 its arrival count, 2 its arrival epoch; the direct variant packs the
+// arrival epochs of all XCCs into the two lines after those (one word each).
 constexpr int kMaxXcc = 16;
-constexpr int kFlagWords = (kMaxBlocks + 3 * kMaxXcc) * kFlagStride;
-// barrier of the solve kernel unless GADI_BARRIER says otherwise (0 relay, 1 XCC-hierarchical)
-constexpr int kDefaultBarrier = 1;
+constexpr int kFlagWords = (kMaxBlocks + 3 * kMaxXcc) * kFlagStride + kMaxXcc;
+// barrier of the solve kernel unless GADI_BARRIER says otherwise (0 relay, 1
+// XCC-hierarchical with a master, 2 XCC-hierarchical without one)
+constexpr int kDefaultBarrier = 2;
 // Per-phase profile of block 0 (ticks [10], counts [10]), then per block the
 // ticks inside barriers [kMaxBlocks] and in the whole launch [kMaxBlocks].
 constexpr int kProfHead = 20;
@@ -104,6 +106,14 @@ struct System {
   // > 0: every slice is diagonal-style with these same dia_uniform offsets
   int dia_uniform = 0;
   int32_t dia_u[kDiaMax] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // the uniform offsets are symmetric about zero (dia_u[k] = -dia_u[W-1-k])
+  bool dia_sym = false;
+  // H and S in the half layout of a symmetric uniform pattern, per value type
+  // (0 fp16, 1 fp32, 2 fp64, 3 E4M3): per slice only the slots of the positive
+  // offsets, with half_pad zero rows in front of row 0; built on first use
+  void* h_half[4] = {nullptr, nullptr, nullptr, nullptr};
+  void* s_half[4] = {nullptr, nullptr, nullptr, nullptr};
+  int half_pad = 0;
   int32_t* slice_ptr = nullptr;  // [nslices + 1]
   int32_t* col = nullptr;        // [nslots]
   double* a_off = nullptr;       // [nslots] A values on the union pattern
@@ -139,8 +149,9 @@ struct System {
   // launch shape of the solve kernel per precision mode, chosen by the autotuner
   int tuned_block[7] = {0, 0, 0, 0, 0, 0, 0};
   int tuned_per_cu[7] = {0, 0, 0, 0, 0, 0, 0};
-  int tuned_fused[7] = {0, 0, 0, 0, 0, 0, 0};
+  int tuned_form[7] = {0, 0, 0, 0, 0, 0, 0};  // inner-solver form (solve_body.h)
   int last_blocks = 0;
+  int last_form = -1;
   int last_block_threads = 0;
 };
 

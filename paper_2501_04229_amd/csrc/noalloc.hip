@@ -12,7 +12,7 @@
 
 namespace gadi {
 
-gadi_status launch_solve_shape(System& s, int prec, SolveArgs a, int block, int per_cu, bool fused);
+gadi_status launch_solve_shape(System& s, int prec, SolveArgs a, int block, int per_cu, int form);
 int barrier_kind();
 double wall_clock_hz();
 
@@ -150,14 +150,22 @@ extern "C" gadi_status gadi_ir_solve_noalloc(gadi_handle* h, const double* b, do
     a.s_off = s.s_off64;
     a.h_diag = s.h_diag64;
   }
+  // the half layout of H and S if a gadi_ir_solve has built it for this
+  // precision, else the full layout through the generic pattern
+  {
+    const int kind = o.prec == GADI_PREC_FP16_IR ? 0 : 2;
+    a.h_half = s.h_half[kind];
+    a.s_half = s.s_half[kind];
+    a.half_pad = s.half_pad;
+  }
   // the launch shape the autotuner chose for this handle and precision (a
   // gadi_ir_solve call tunes it), else one 1024-thread block per compute unit
-  // with the Chronopoulos-Gear inner solves
+  // with the pipelined CG and Craig's CGNE
   const int p = o.prec;
   const int block = s.tuned_block[p] ? s.tuned_block[p] : 1024;
   const int per_cu = s.tuned_block[p] ? s.tuned_per_cu[p] : 1;
-  const bool fused = s.tuned_block[p] ? s.tuned_fused[p] != 0 : true;
-  if ((st = launch_solve_shape(s, p, a, block, per_cu, fused)) != GADI_OK) return st;
+  const int form = s.tuned_block[p] ? s.tuned_form[p] : 2;
+  if ((st = launch_solve_shape(s, p, a, block, per_cu, form)) != GADI_OK) return st;
   GADI_HIP_CHECK(hipMemcpyAsync(x, dx, sizeof(double) * s.n, hipMemcpyDeviceToDevice, s.stream));
   DevInfo di;
   int abort_flag = 0;

@@ -71,6 +71,10 @@ void free_system(System& s) {
                   s.hist,      s.sync,    s.flags,   s.part,    s.result,  s.info, s.prof, s.h_off8, s.s_off8};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  for (int k = 0; k < 4; ++k) {
+    if (s.h_half[k]) (void)hipFree(s.h_half[k]);
+    if (s.s_half[k]) (void)hipFree(s.s_half[k]);
+  }
   if (s.ev0) (void)hipEventDestroy(s.ev0);
   if (s.ev1) (void)hipEventDestroy(s.ev1);
   s = System();
@@ -313,6 +317,9 @@ extern "C" gadi_status gadi_setup(const gadi_csr* A, gadi_splitting split, gadi_
   S.dia_slices = dia_slices;
   S.dia_uniform = dia_uniform;
   for (int k = 0; k < dia_uniform; ++k) S.dia_u[k] = uni[k];
+  S.dia_sym = dia_uniform > 0;
+  for (int k = 0; k < dia_uniform; ++k)
+    if (uni[k] != -uni[dia_uniform - 1 - k]) S.dia_sym = false;
   int64_t dslots = 0, expl = 0;
   for (int sl = 0; sl < nslices; ++sl) {
     const int64_t slots = (int64_t)(slice_ptr[sl + 1] - slice_ptr[sl]);

@@ -48,10 +48,16 @@ int num_cus() { return g_num_cus; }
 // Device-wide barrier of the solve kernel: 1 = XCC-hierarchical (one L2
 // writeback per XCC and phase), 0 = relay through block 0 with every block's
 // own release; GADI_BARRIER=relay|xcc overrides the default.
+bool generic_pattern_forced() {
+  const char* e = std::getenv("GADI_SOLVE_PATTERN");
+  return e && std::string(e) == "generic";
+}
+
 int barrier_kind() {
   const char* e = std::getenv("GADI_BARRIER");
   if (e && std::string(e) == "relay") return 0;
   if (e && std::string(e) == "xcc") return 1;
+  if (e && std::string(e) == "direct") return 2;
   return kDefaultBarrier;
 }
 
@@ -110,6 +116,61 @@ __global__ void widen_kernel(const float* __restrict__ in, double* __restrict__ 
 __global__ void fill_zero_kernel(double* __restrict__ p, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     p[i] = 0.0;
+}
+
+// Half layout of a symmetric uniform pattern (PatDiaSym): slice sl of the
+// half array holds, for its 64 rows, the slots of the W/2 positive offsets of
+// the full array's slice sl - P; the P leading slices are zero.
+template <class T>
+__global__ void halve_kernel(const T* __restrict__ full, T* __restrict__ half, long long nhalf, int W, long long P) {
+  const int H = W / 2;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nhalf; i += (long long)gridDim.x * blockDim.x) {
+    const long long sl = i / (H * kSlice);
+    const long long rem = i - sl * H * kSlice;
+    const long long q = rem / kSlice, l = rem - q * kSlice;
+    half[i] = sl < P ? T(0) : full[(sl - P) * W * kSlice + (H + q) * kSlice + l];
+  }
+}
+
+template <class T>
+static gadi_status halve(System& s, const void* full, void** out, long long nhalf, long long P) {
+  GADI_HIP_CHECK(hipMalloc(out, sizeof(T) * (size_t)nhalf));
+  hipLaunchKernelGGL(halve_kernel<T>, dim3(1024), dim3(256), 0, s.stream, (const T*)full, (T*)*out, nhalf,
+                     s.dia_uniform, P);
+  GADI_HIP_CHECK(hipGetLastError());
+  return GADI_OK;
+}
+
+// The half layout of H and S for value type `kind` (0 fp16, 1 fp32, 2 fp64,
+// 3 E4M3) from their full arrays, once per handle and type.
+gadi_status ensure_half(System& s, int kind, const void* hfull, const void* sfull) {
+  if (!s.dia_sym || s.h_half[kind]) return GADI_OK;
+  const long long P = (s.dia_u[s.dia_uniform - 1] + kSlice - 1) / kSlice;
+  const long long nhalf = (P + s.nslices) * (long long)(s.dia_uniform / 2) * kSlice;
+  s.half_pad = (int)(P * kSlice);
+  gadi_status st = GADI_OK;
+  void *h = nullptr, *sv = nullptr;
+  switch (kind) {
+    case 0:
+      if ((st = halve<uint16_t>(s, hfull, &h, nhalf, P)) == GADI_OK) st = halve<uint16_t>(s, sfull, &sv, nhalf, P);
+      break;
+    case 1:
+      if ((st = halve<uint32_t>(s, hfull, &h, nhalf, P)) == GADI_OK) st = halve<uint32_t>(s, sfull, &sv, nhalf, P);
+      break;
+    case 2:
+      if ((st = halve<uint64_t>(s, hfull, &h, nhalf, P)) == GADI_OK) st = halve<uint64_t>(s, sfull, &sv, nhalf, P);
+      break;
+    default:
+      if ((st = halve<uint8_t>(s, hfull, &h, nhalf, P)) == GADI_OK) st = halve<uint8_t>(s, sfull, &sv, nhalf, P);
+  }
+  if (st != GADI_OK) {
+    if (h) (void)hipFree(h);
+    if (sv) (void)hipFree(sv);
+    return st;
+  }
+  s.h_half[kind] = h;
+  s.s_half[kind] = sv;
+  return GADI_OK;
 }
 
 gadi_status ensure_fp32_public(System& s) { return ensure_fp32(s); }
@@ -188,32 +249,39 @@ gadi_status ensure_fp8_public(System& s) { return ensure_fp8(s); }
 #define GADI_MODES(X) X(ModeF16) X(ModeF32) X(ModeF64) X(ModeHDS) X(ModeHSS) X(ModeSSS) X(ModeF8)
 GADI_MODES(GADI_DECLARE_MODE)
 
-// fused: Chronopoulos-Gear inner solves (one reduction per CG step) instead of
-// Hestenes-Stiefel (two)
-template <bool FUSED>
+// form: the inner-solver form (0 Hestenes-Stiefel, 1 Chronopoulos-Gear, 2
+// pipelined CG with Craig's CGNE, 3 Hestenes-Stiefel CG with Craig's CGNE)
+template <int FORM>
 static gadi_status launch_prec(System& s, int prec, const SolveArgs& a, int block, int per_cu) {
   switch (prec) {
-    case GADI_PREC_FP16_IR: return launch_mode<ModeF16, FUSED>(s, a, block, per_cu);
-    case GADI_PREC_FP32_IR: return launch_mode<ModeF32, FUSED>(s, a, block, per_cu);
-    case GADI_PREC_H_D_S: return launch_mode<ModeHDS, FUSED>(s, a, block, per_cu);
-    case GADI_PREC_H_S_S: return launch_mode<ModeHSS, FUSED>(s, a, block, per_cu);
-    case GADI_PREC_S_S_S: return launch_mode<ModeSSS, FUSED>(s, a, block, per_cu);
-    case GADI_PREC_FP8_IR: return launch_mode<ModeF8, FUSED>(s, a, block, per_cu);
+    case GADI_PREC_FP16_IR: return launch_mode<ModeF16, FORM>(s, a, block, per_cu);
+    case GADI_PREC_FP32_IR: return launch_mode<ModeF32, FORM>(s, a, block, per_cu);
+    case GADI_PREC_H_D_S: return launch_mode<ModeHDS, FORM>(s, a, block, per_cu);
+    case GADI_PREC_H_S_S: return launch_mode<ModeHSS, FORM>(s, a, block, per_cu);
+    case GADI_PREC_S_S_S: return launch_mode<ModeSSS, FORM>(s, a, block, per_cu);
+    case GADI_PREC_FP8_IR: return launch_mode<ModeF8, FORM>(s, a, block, per_cu);
   }
-  return launch_mode<ModeF64, FUSED>(s, a, block, per_cu);
+  return launch_mode<ModeF64, FORM>(s, a, block, per_cu);
 }
 
-static gadi_status launch_solve(System& s, int prec, const SolveArgs& a, int block, int per_cu, bool fused) {
-  return fused ? launch_prec<true>(s, prec, a, block, per_cu) : launch_prec<false>(s, prec, a, block, per_cu);
+static gadi_status launch_solve(System& s, int prec, const SolveArgs& a, int block, int per_cu, int form) {
+  s.last_form = form;
+  switch (form) {
+    case 0: return launch_prec<0>(s, prec, a, block, per_cu);
+    case 1: return launch_prec<1>(s, prec, a, block, per_cu);
+    case 2: return launch_prec<2>(s, prec, a, block, per_cu);
+    case 3: return launch_prec<3>(s, prec, a, block, per_cu);
+  }
+  return GADI_EINVAL;
 }
 
 // for the allocation-free entry point (noalloc.hip): the same launch with the
 // synchronisation state and vectors the caller's SolveArgs name
-gadi_status launch_solve_shape(System& s, int prec, SolveArgs a, int block, int per_cu, bool fused) {
+gadi_status launch_solve_shape(System& s, int prec, SolveArgs a, int block, int per_cu, int form) {
   gadi_status st = device_props();
   if (st != GADI_OK) return st;
   a.timeout = barrier_timeout_ticks();
-  return launch_solve(s, prec, a, block, per_cu, fused);
+  return launch_solve(s, prec, a, block, per_cu, form);
 }
 
 double wall_clock_hz() { return (double)g_wall_rate_khz * 1000.0; }
@@ -226,24 +294,27 @@ static bool single_residual(int prec) {
 }
 
 // Autotuner: time three outer sweeps from x = 0 in every candidate (threads
-// per block x blocks per compute unit x inner-solver variant), after one
+// per block x blocks per compute unit x inner-solver form), after one
 // untimed warm-up launch, best of two passes, and keep the lowest time per
 // inner step.  Runs once per handle and precision; GADI_SOLVE_BLOCK,
-// GADI_BLOCKS_PER_CU and GADI_SOLVE_FUSED override it.
+// GADI_BLOCKS_PER_CU and GADI_SOLVE_FORM override it.
 static gadi_status tune_solve(System& s, int prec, SolveArgs a, double* dx) {
   if (s.tuned_block[prec]) return GADI_OK;
   const char* eb = std::getenv("GADI_SOLVE_BLOCK");
   const char* ec = std::getenv("GADI_BLOCKS_PER_CU");
-  const char* ef = std::getenv("GADI_SOLVE_FUSED");
+  const char* ef = std::getenv("GADI_SOLVE_FORM");
   if (eb || ec || ef) {
     s.tuned_block[prec] = eb ? std::atoi(eb) : 1024;
     s.tuned_per_cu[prec] = ec ? std::atoi(ec) : 1;
-    s.tuned_fused[prec] = ef ? (std::atoi(ef) != 0) : 0;
+    s.tuned_form[prec] = ef ? std::atoi(ef) : 2;
     return GADI_OK;
   }
-  // {threads per block, blocks per CU, fused inner solves}
+  // {threads per block, blocks per CU, inner-solver form}
+  // (shapes that are not co-resident return EINVAL and are skipped)
   static const int cand[][3] = {{1024, 1, 0}, {1024, 2, 0}, {512, 4, 0}, {512, 2, 0}, {512, 1, 0},
-                                {1024, 1, 1}, {1024, 2, 1}, {512, 4, 1}, {512, 2, 1}};
+                                {1024, 1, 1}, {1024, 2, 1}, {512, 4, 1}, {512, 2, 1}, {512, 1, 1},
+                                {1024, 1, 2}, {1024, 2, 2}, {512, 4, 2}, {512, 2, 2}, {512, 1, 2},
+                                {1024, 1, 3}, {1024, 2, 3}, {512, 4, 3}, {512, 2, 3}, {512, 1, 3}};
   a.maxit_out = a.maxit_out < 3 ? a.maxit_out : 3;
   a.hist = nullptr;
   a.hist_cap = 0;
@@ -254,7 +325,7 @@ static gadi_status tune_solve(System& s, int prec, SolveArgs a, double* dx) {
     for (const auto& c : cand) {
       hipLaunchKernelGGL(fill_zero_kernel, dim3(256), dim3(256), 0, s.stream, dx, (long long)s.npad);
       GADI_HIP_CHECK(hipEventRecord(s.ev0, s.stream));
-      gadi_status st = launch_solve(s, prec, a, c[0], c[1], c[2] != 0);
+      gadi_status st = launch_solve(s, prec, a, c[0], c[1], c[2]);
       if (st == GADI_EINVAL) continue;
       if (st != GADI_OK) return st;
       GADI_HIP_CHECK(hipEventRecord(s.ev1, s.stream));
@@ -268,7 +339,7 @@ static gadi_status tune_solve(System& s, int prec, SolveArgs a, double* dx) {
       const double per = ms / (steps > 0 ? steps : 1.0);
       if (pass == 0) break;  // warm-up launch only
       if (std::getenv("GADI_DEBUG"))
-        std::fprintf(stderr, "gadi: tune prec %d block %d x %d/CU fused %d: %.2f us/step (%lld phases)\n", prec,
+        std::fprintf(stderr, "gadi: tune prec %d block %d x %d/CU form %d: %.2f us/step (%lld phases)\n", prec,
                      c[0], c[1], c[2], per * 1e3, (long long)di.barriers);
       if (per < best) {
         best = per;
@@ -280,7 +351,7 @@ static gadi_status tune_solve(System& s, int prec, SolveArgs a, double* dx) {
   }
   s.tuned_block[prec] = bb;
   s.tuned_per_cu[prec] = bc;
-  s.tuned_fused[prec] = bf;
+  s.tuned_form[prec] = bf;
   return GADI_OK;
 }
 
@@ -392,6 +463,16 @@ extern "C" gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x,
     a.s_off = s.s_off64;
     a.h_diag = s.h_diag64;
   }
+  {
+    const int kind = (o.prec == GADI_PREC_FP16_IR || o.prec == GADI_PREC_H_D_S || o.prec == GADI_PREC_H_S_S) ? 0
+                     : o.prec == GADI_PREC_FP8_IR                                                      ? 3
+                     : inner32                                                                          ? 1
+                                                                                                        : 2;
+    if ((st = ensure_half(s, kind, a.h_off, a.s_off)) != GADI_OK) return st;
+    a.h_half = s.h_half[kind];
+    a.s_half = s.s_half[kind];
+    a.half_pad = s.half_pad;
+  }
   if ((st = tune_solve(s, o.prec, a, dx)) != GADI_OK) return st;
   // a single-precision solution lives in dx as floats; the caller's doubles
   // pass through the staging vector after the Krylov vectors
@@ -404,7 +485,7 @@ extern "C" gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x,
     GADI_HIP_CHECK(hipGetLastError());
   }
   GADI_HIP_CHECK(hipEventRecord(s.ev0, s.stream));
-  st = launch_solve(s, o.prec, a, s.tuned_block[o.prec], s.tuned_per_cu[o.prec], s.tuned_fused[o.prec] != 0);
+  st = launch_solve(s, o.prec, a, s.tuned_block[o.prec], s.tuned_per_cu[o.prec], s.tuned_form[o.prec]);
   if (st != GADI_OK) return st;
   GADI_HIP_CHECK(hipEventRecord(s.ev1, s.stream));
   if (xs) {
@@ -458,6 +539,8 @@ extern "C" int32_t gadi_solver_blocks(gadi_handle* h, int32_t* threads) {
   if (threads) *threads = h->sys.last_block_threads;
   return h->sys.last_blocks;
 }
+
+extern "C" int32_t gadi_solver_form(gadi_handle* h) { return h ? h->sys.last_form : -1; }
 
 extern "C" int32_t gadi_get_block_profile(gadi_handle* h, double* wait_seconds, double* total_seconds, int32_t cap) {
   if (!h || !h->sys.prof || h->sys.last_blocks <= 0) return 0;

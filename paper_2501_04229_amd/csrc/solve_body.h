@@ -41,6 +41,11 @@ struct SolveArgs {
   const void* h_off;
   const void* s_off;
   const void* h_diag;
+  // H and S in the half layout of the uniform pattern (the positive offsets
+  // only, half_pad zero rows in front; System::h_half), or null
+  const void* h_half;
+  const void* s_half;
+  int half_pad;
   const double* b;
   void* x;  // Mode::XT solution
   void* r;
@@ -61,7 +66,7 @@ struct SolveArgs {
   unsigned long long* prune;
   // optional per-phase profile of block 0: wall-clock ticks [10], phase counts [10]
   long long* prof;
-  int barrier;  // device-wide barrier: 0 relay, 1 XCC-hierarchical
+  int barrier;  // device-wide barrier: 0 relay, 1 XCC-hierarchical, 2 XCC-hierarchical without a master
 };
 
 // Reduction into out[4] under the caller's synchronisation policy; leaves the
@@ -198,6 +203,10 @@ template <int W>
 struct PatDia {
   int off[W];
   int nmax;
+  template <bool SKEW, class MT>
+  __device__ __forceinline__ const MT* mirror(const MT* p, const MT*) const {
+    return p;
+  }
   template <class MT, class R>
   struct G {
     MT v[W];
@@ -227,8 +236,72 @@ struct PatDia {
   }
 };
 
+// Values of a matrix that is symmetric (SKEW = false: H) or skew-symmetric
+// (SKEW = true: S) in value, as PatDiaSym reads them.
+template <class MT, bool SKEW>
+struct MirrorVals {
+  const MT* p;
+};
+
+template <class MT>
+__device__ __forceinline__ MT neg_of(MT v) {
+  return -v;
+}
+template <>
+__device__ __forceinline__ __half neg_of(__half v) {
+  return __hneg(v);
+}
+template <>
+__device__ __forceinline__ e4m3 neg_of(e4m3 v) {
+  return e4m3{(uint8_t)(v.bits ^ 0x80u)};
+}
+
+// PatDia<W> for the symmetric offset sets of H and S (off[j] = -off[W-1-j],
+// ascending: the pattern is that of A + A^T).  H_ij = H_ji and S_ij = -S_ji
+// hold exactly for the stored values (both entries are computed from the same
+// A_ij, A_ji and rounded to nearest, which commutes with negation), so H and S
+// are read from a half layout that keeps the W/2 positive offsets of each row
+// (W/2 slots per slice, `pad` zero rows in front): the entry at offset -d of
+// row i is the entry at +d of row i - d (negated for S).  Both reads are
+// contiguous streams; the value bytes of the H and S products halve, and every
+// value is the one the full layout stores (a zero may change sign), so the
+// products are those of PatDia.  Plain pointers (A) take the full layout.
+template <int W>
+struct PatDiaSym : PatDia<W> {
+  int pad;  // zero rows in front of row 0 of the half layout (a multiple of kSlice, >= off[W-1])
+  using PatDia<W>::gather;
+  template <bool SKEW, class MT>
+  __device__ __forceinline__ MirrorVals<MT, SKEW> mirror(const MT*, const MT* half) const {
+    return {half};
+  }
+  template <class MT, bool SKEW, class LD>
+  __device__ __forceinline__ auto gather(unsigned row, MirrorVals<MT, SKEW> mv, LD&& load) const {
+    constexpr int H = W / 2;
+    typename PatDia<W>::template G<MT, decltype(load(0u))> g;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const int cc = (int)row + this->off[j];
+      g.x[j] = load((unsigned)(cc < 0 ? 0 : (cc > this->nmax ? this->nmax : cc)));
+      // row rr of the half layout holds the entries at +d; a negative offset
+      // reads the mirrored slot of row cc
+      const unsigned rr = (unsigned)((j >= H ? (int)row : cc) + pad);
+      const int slot = j >= H ? j - H : W - 1 - j - H;
+      MT v = at(mv.p, (rr & ~(unsigned)(kSlice - 1)) * H + (unsigned)(slot * kSlice) + (rr & (kSlice - 1)));
+      if constexpr (SKEW) {
+        if (j < H) v = neg_of(v);
+      }
+      g.v[j] = v;
+    }
+    return g;
+  }
+};
+
 struct PatGeneric {
   Pattern p;
+  template <bool SKEW, class MT>
+  __device__ __forceinline__ const MT* mirror(const MT* p, const MT*) const {
+    return p;
+  }
   template <class MT, class LD>
   struct G {
     int row;
@@ -293,10 +366,10 @@ __device__ __forceinline__ T* pick(int k, T* p0, T* p1) {
 // The refinement loop of Algorithm 1 for rows [t0 * BLOCK, t1 * BLOCK) of one
 // system.  Returns false if a barrier timed out; otherwise fills `res`.
 //
-// Both inner solves exist in two forms.  FUSED = true: the Chronopoulos-Gear
-// form of CG: with w = K r and s = K p carried by recurrence, the two inner
-// products of a step, gamma = r.r and delta = r.K r, come from one reduction.
-// Step k updates
+// The inner solves exist in three forms (FORM).
+// FORM 1: the Chronopoulos-Gear form of CG: with w = K r and s = K p carried
+// by recurrence, the two inner products of a step, gamma = r.r and delta =
+// r.K r, come from one reduction.  Step k updates
 //   s_k = w_k + beta_k s_{k-1},  p_k = r_k + beta_k p_{k-1},
 //   z += a_k p_k,  r_{k+1} = r_k - a_k s_k,  w_{k+1} = K r_{k+1},
 // with beta_k = gamma_k / gamma_{k-1} and a_k = gamma_k / (delta_k - beta_k gamma_k / a_{k-1}).
@@ -307,10 +380,22 @@ __device__ __forceinline__ T* pick(int k, T* p0, T* p1) {
 // roundings as their owner, so every copy is bit-identical.  A CG step on
 // alpha I + H is one phase; a CGNE step on I - (S/alpha)^2 is two (the
 // second product needs the first one's result at neighbouring rows).
-// FUSED = false: Hestenes-Stiefel CG with q_{k+1} = K p_{k+1} = K r_{k+1} +
+// FORM 0: Hestenes-Stiefel CG with q_{k+1} = K p_{k+1} = K r_{k+1} +
 // beta q_k folded into the product phase: two phases per CG step, three per
 // CGNE step, and no recomputation.
-template <class Mode, int BLOCK, bool FUSED, int U, class Red, class Pat>
+// FORM 2: the same Chronopoulos-Gear scalars with one more recurrence,
+// u_k = K s_k = K w_k + beta_k u_{k-1}, so that the step's product is K w_k
+// on a vector the previous phase completed (the pipelined arrangement of
+// Ghysels and Vanroose): one phase per CG step and no recomputation, w in
+// ping-pong buffers.  Its CGNE is Craig's method on (I + S/alpha) y = g:
+//   v = (I + S/alpha) p_k,  y += a_k p_k,  r_{k+1} = r_k - a_k v,
+//   p_{k+1} = (I - S/alpha) r_{k+1} + beta_k p_k,
+// a_k = |r_k|^2 / |p_k|^2, beta_k = |r_{k+1}|^2 / |r_k|^2: two phases per
+// step, one product each, and y = (I - S/alpha) w comes out directly, so the
+// update a6 needs no product.  In exact arithmetic its iterates are those of
+// CG on (I - (S/alpha)^2) w = g mapped by I - S/alpha, with the same residuals.
+// FORM 3: the Hestenes-Stiefel CG of form 0 with Craig's CGNE of form 2.
+template <class Mode, int BLOCK, int FORM, int U, class Red, class Pat>
 __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const Pat& pat, int t0, int t1,
                                            DevInfo& res_out) {
   using MT = typename Mode::MT;
@@ -321,6 +406,9 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
 
   const MT* __restrict__ hoff = (const MT*)a.h_off;
   const MT* __restrict__ soff = (const MT*)a.s_off;
+  // H and S as the pattern reads them (the symmetric pattern reads half of each)
+  const auto hv = pat.template mirror<false>(hoff, (const MT*)a.h_half);
+  const auto sv = pat.template mirror<true>(soff, (const MT*)a.s_half);
   using DT = typename Mode::DT;
   const DT* __restrict__ hdiag = (const DT*)a.h_diag;
   RT* __restrict__ r = (RT*)a.r;
@@ -432,7 +520,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
     double zmax = 0.0;
     int it = 0;
     auto gr = [&](unsigned c) { return at(r, c); };
-    if constexpr (FUSED) {
+    if constexpr (FORM == 1 || FORM == 2) {
       struct RW {
         AT r, w;
       };
@@ -445,8 +533,8 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
               struct {
                 RT rr;
                 DT hd;
-                decltype(pat.gather(0u, hoff, gr)) g;
-              } l{at(r, row), at(hdiag, row), pat.gather(row, hoff, gr)};
+                decltype(pat.gather(0u, hv, gr)) g;
+              } l{at(r, row), at(hdiag, row), pat.gather(row, hv, gr)};
               return l;
             },
             [&](const auto& l) {
@@ -475,81 +563,154 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
           }
           const double ak = gam / den;
           const AT akt = (AT)ak, bkt = (AT)beta;
-          const VT* __restrict__ rk = pick(k, R0, R1);
-          const VT* __restrict__ wk = pick(k, W0, W1);
-          const VT* __restrict__ sprev = pick(k + 1, S0, S1);
-          VT* __restrict__ snew = pick(k, S0, S1);
-          VT* __restrict__ rnew = pick(k + 1, R0, R1);
-          VT* __restrict__ wnew = pick(k + 1, W0, W1);
           double g1 = 0.0, d1 = 0.0, m3 = 0.0;
-          struct O {
-            AT s, p, rn, wn;
-            ST z;
-          };
-          auto store = [&](unsigned row, const O& o) {
-            at(snew, row) = st<VT>(o.s);
-            at(P, row) = st<VT>(o.p);
-            at(z, row) = o.z;
-            at(rnew, row) = st<VT>(o.rn);
-            at(wnew, row) = st<VT>(o.wn);
-            g1 += (double)o.rn * (double)o.rn;
-            d1 += (double)o.wn * (double)o.rn;
-            m3 = fmax(m3, fabs((double)o.z));
-          };
-          if (k == 0) {
-            // s_0 = w_0, p_0 = r_0; r_1 at row c = r_0 - a_0 w_0
-            auto gl = [&](unsigned c) { return Rk2{at(wk, c), at(rk, c)}; };
-            auto r_next = [&](const Rk2& v) { return rnd(fma_at<AT>(-akt, ldv(v.w), ldv(v.r))); };
-            for_rows<BLOCK, U>(
-                t0, t1,
-                [&](unsigned row) {
-                  struct {
-                    VT r, w;
-                    DT hd;
-                    decltype(pat.gather(0u, hoff, gl)) g;
-                  } l{at(rk, row), at(wk, row), at(hdiag, row), pat.gather(row, hoff, gl)};
-                  return l;
-                },
-                [&](const auto& l) {
-                  O o;
-                  const AT ri = ldv(l.r);
-                  o.s = ldv(l.w);
-                  o.p = ri;
-                  o.z = (ST)(akt * ri);
-                  o.rn = rnd(fma_at<AT>(-akt, o.s, ri));
-                  o.wn = rnd((alpha + ld<AT>(l.hd)) * o.rn + pat.template dot<AT>(l.g, r_next));
-                  return o;
-                },
-                store);
-          } else {
-            // s_k = w_k + b_k s_{k-1} and r_{k+1} = r_k - a_k s_k at row c,
-            // computed exactly as the row's owner computes them
-            auto gl = [&](unsigned c) { return Rk3{at(sprev, c), at(wk, c), at(rk, c)}; };
-            auto r_next = [&](const Rk3& v) {
-              return rnd(fma_at<AT>(-akt, rnd(fma_at<AT>(bkt, ldv(v.sp), ldv(v.w))), ldv(v.r)));
+          if constexpr (FORM == 1) {
+            const VT* __restrict__ rk = pick(k, R0, R1);
+            const VT* __restrict__ wk = pick(k, W0, W1);
+            const VT* __restrict__ sprev = pick(k + 1, S0, S1);
+            VT* __restrict__ snew = pick(k, S0, S1);
+            VT* __restrict__ rnew = pick(k + 1, R0, R1);
+            VT* __restrict__ wnew = pick(k + 1, W0, W1);
+            struct O {
+              AT s, p, rn, wn;
+              ST z;
             };
-            for_rows<BLOCK, U>(
-                t0, t1,
-                [&](unsigned row) {
-                  struct {
-                    VT r, w, sp, p;
-                    ST z;
-                    DT hd;
-                    decltype(pat.gather(0u, hoff, gl)) g;
-                  } l{at(rk, row), at(wk, row), at(sprev, row), at(P, row), at(z, row), at(hdiag, row), pat.gather(row, hoff, gl)};
-                  return l;
-                },
-                [&](const auto& l) {
-                  O o;
-                  const AT ri = ldv(l.r);
-                  o.s = rnd(fma_at<AT>(bkt, ldv(l.sp), ldv(l.w)));
-                  o.p = rnd(fma_at<AT>(bkt, ldv(l.p), ri));
-                  o.z = l.z + (ST)(akt * o.p);
-                  o.rn = rnd(fma_at<AT>(-akt, o.s, ri));
-                  o.wn = rnd((alpha + ld<AT>(l.hd)) * o.rn + pat.template dot<AT>(l.g, r_next));
-                  return o;
-                },
-                store);
+            auto store = [&](unsigned row, const O& o) {
+              at(snew, row) = st<VT>(o.s);
+              at(P, row) = st<VT>(o.p);
+              at(z, row) = o.z;
+              at(rnew, row) = st<VT>(o.rn);
+              at(wnew, row) = st<VT>(o.wn);
+              g1 += (double)o.rn * (double)o.rn;
+              d1 += (double)o.wn * (double)o.rn;
+              m3 = fmax(m3, fabs((double)o.z));
+            };
+            if (k == 0) {
+              // s_0 = w_0, p_0 = r_0; r_1 at row c = r_0 - a_0 w_0
+              auto gl = [&](unsigned c) { return Rk2{at(wk, c), at(rk, c)}; };
+              auto r_next = [&](const Rk2& v) { return rnd(fma_at<AT>(-akt, ldv(v.w), ldv(v.r))); };
+              for_rows<BLOCK, U>(
+                  t0, t1,
+                  [&](unsigned row) {
+                    struct {
+                      VT r, w;
+                      DT hd;
+                      decltype(pat.gather(0u, hv, gl)) g;
+                    } l{at(rk, row), at(wk, row), at(hdiag, row), pat.gather(row, hv, gl)};
+                    return l;
+                  },
+                  [&](const auto& l) {
+                    O o;
+                    const AT ri = ldv(l.r);
+                    o.s = ldv(l.w);
+                    o.p = ri;
+                    o.z = (ST)(akt * ri);
+                    o.rn = rnd(fma_at<AT>(-akt, o.s, ri));
+                    o.wn = rnd((alpha + ld<AT>(l.hd)) * o.rn + pat.template dot<AT>(l.g, r_next));
+                    return o;
+                  },
+                  store);
+            } else {
+              // s_k = w_k + b_k s_{k-1} and r_{k+1} = r_k - a_k s_k at row c,
+              // computed exactly as the row's owner computes them
+              auto gl = [&](unsigned c) { return Rk3{at(sprev, c), at(wk, c), at(rk, c)}; };
+              auto r_next = [&](const Rk3& v) {
+                return rnd(fma_at<AT>(-akt, rnd(fma_at<AT>(bkt, ldv(v.sp), ldv(v.w))), ldv(v.r)));
+              };
+              for_rows<BLOCK, U>(
+                  t0, t1,
+                  [&](unsigned row) {
+                    struct {
+                      VT r, w, sp, p;
+                      ST z;
+                      DT hd;
+                      decltype(pat.gather(0u, hv, gl)) g;
+                    } l{at(rk, row), at(wk, row), at(sprev, row), at(P, row), at(z, row), at(hdiag, row), pat.gather(row, hv, gl)};
+                    return l;
+                  },
+                  [&](const auto& l) {
+                    O o;
+                    const AT ri = ldv(l.r);
+                    o.s = rnd(fma_at<AT>(bkt, ldv(l.sp), ldv(l.w)));
+                    o.p = rnd(fma_at<AT>(bkt, ldv(l.p), ri));
+                    o.z = l.z + (ST)(akt * o.p);
+                    o.rn = rnd(fma_at<AT>(-akt, o.s, ri));
+                    o.wn = rnd((alpha + ld<AT>(l.hd)) * o.rn + pat.template dot<AT>(l.g, r_next));
+                    return o;
+                  },
+                  store);
+            }
+          } else {
+            // pipelined: the product is K w_k; r stays in R0, s in S0, u in S1
+            const VT* __restrict__ wk = pick(k, W0, W1);
+            VT* __restrict__ wnew = pick(k + 1, W0, W1);
+            auto gw = [&](unsigned c) { return at(wk, c); };
+            struct O {
+              AT s, u, p, rn, wn;
+              ST z;
+            };
+            auto store = [&](unsigned row, const O& o) {
+              at(S0, row) = st<VT>(o.s);
+              at(S1, row) = st<VT>(o.u);
+              at(P, row) = st<VT>(o.p);
+              at(z, row) = o.z;
+              at(R0, row) = st<VT>(o.rn);
+              at(wnew, row) = st<VT>(o.wn);
+              g1 += (double)o.rn * (double)o.rn;
+              d1 += (double)o.wn * (double)o.rn;
+              m3 = fmax(m3, fabs((double)o.z));
+            };
+            if (k == 0) {
+              // u_0 = K w_0, s_0 = w_0, p_0 = r_0
+              for_rows<BLOCK, U>(
+                  t0, t1,
+                  [&](unsigned row) {
+                    struct {
+                      VT r, w;
+                      DT hd;
+                      decltype(pat.gather(0u, hv, gw)) g;
+                    } l{at(R0, row), at(wk, row), at(hdiag, row), pat.gather(row, hv, gw)};
+                    return l;
+                  },
+                  [&](const auto& l) {
+                    O o;
+                    const AT ri = ldv(l.r), wi = ldv(l.w);
+                    o.u = rnd((alpha + ld<AT>(l.hd)) * wi + pat.template dot<AT>(l.g, ldv));
+                    o.s = wi;
+                    o.p = ri;
+                    o.z = (ST)(akt * ri);
+                    o.rn = rnd(fma_at<AT>(-akt, o.s, ri));
+                    o.wn = rnd(fma_at<AT>(-akt, o.u, wi));
+                    return o;
+                  },
+                  store);
+            } else {
+              for_rows<BLOCK, U>(
+                  t0, t1,
+                  [&](unsigned row) {
+                    struct {
+                      VT r, w, s, u, p;
+                      ST z;
+                      DT hd;
+                      decltype(pat.gather(0u, hv, gw)) g;
+                    } l{at(R0, row), at(wk, row), at(S0, row), at(S1, row), at(P, row), at(z, row), at(hdiag, row),
+                        pat.gather(row, hv, gw)};
+                    return l;
+                  },
+                  [&](const auto& l) {
+                    O o;
+                    const AT ri = ldv(l.r), wi = ldv(l.w);
+                    const AT kw = (alpha + ld<AT>(l.hd)) * wi + pat.template dot<AT>(l.g, ldv);
+                    o.u = rnd(fma_at<AT>(bkt, ldv(l.u), kw));
+                    o.s = rnd(fma_at<AT>(bkt, ldv(l.s), wi));
+                    o.p = rnd(fma_at<AT>(bkt, ldv(l.p), ri));
+                    o.z = l.z + (ST)(akt * o.p);
+                    o.rn = rnd(fma_at<AT>(-akt, o.s, ri));
+                    o.wn = rnd(fma_at<AT>(-akt, o.u, wi));
+                    return o;
+                  },
+                  store);
+            }
           }
           ALLREDUCE_P(2, g1, d1, 0.0, m3);
           gam_prev = gam;
@@ -577,8 +738,8 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
               struct {
                 RT rr;
                 DT hd;
-                decltype(pat.gather(0u, hoff, gr)) g;
-              } l{at(r, row), at(hdiag, row), pat.gather(row, hoff, gr)};
+                decltype(pat.gather(0u, hv, gr)) g;
+              } l{at(r, row), at(hdiag, row), pat.gather(row, hv, gr)};
               return l;
             },
             [&](const auto& l) {
@@ -658,8 +819,8 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                   struct {
                     VT r, p, q;
                     DT hd;
-                    decltype(pat.gather(0u, hoff, gv)) g;
-                  } l{at(vr, row), at(vp, row), at(vq, row), at(hdiag, row), pat.gather(row, hoff, gv)};
+                    decltype(pat.gather(0u, hv, gv)) g;
+                  } l{at(vr, row), at(vp, row), at(vq, row), at(hdiag, row), pat.gather(row, hv, gv)};
                   return l;
                 },
                 [&](const auto& l) {
@@ -696,7 +857,125 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
       auto g_of = [&](ST zc) { return rnd(two_m_omega * (AT)zc * sc2); };
       auto gz = [&](unsigned c) { return at(z, c); };
       auto gT = [&](unsigned c) { return at(T, c); };
-      if constexpr (FUSED) {
+      if constexpr (FORM >= 2) {
+        // Craig's method: r in R0, p in P, y in wsol
+        double gs0, pp;
+        {
+          // r_0 = g, p_0 = (I - S/alpha) g
+          struct O {
+            AT g, p;
+          };
+          double s0 = 0.0, s1 = 0.0;
+          for_rows<BLOCK, U>(
+              t0, t1,
+              [&](unsigned row) {
+                struct {
+                  ST z;
+                  decltype(pat.gather(0u, sv, gz)) g;
+                } l{at(z, row), pat.gather(row, sv, gz)};
+                return l;
+              },
+              [&](const auto& l) {
+                const AT gi = g_of(l.z);
+                return O{gi, rnd(gi - inv_alpha * pat.template dot<AT>(l.g, g_of))};
+              },
+              [&](unsigned row, const O& o) {
+                at(R0, row) = st<VT>(o.g);
+                at(P, row) = st<VT>(o.p);
+                s0 += (double)o.g * (double)o.g;
+                s1 += (double)o.p * (double)o.p;
+              });
+          ALLREDUCE_P(4, s0, s1, 0.0, 0.0);
+          gs0 = out[0];
+          pp = out[1];
+        }
+        double gam = gs0;
+        if (gs0 > 0.0) {
+          auto gp = [&](unsigned c) { return at(P, c); };
+          auto gr0 = [&](unsigned c) { return at(R0, c); };
+          for (;;) {
+            if (!(pp > 0.0) || !isfinite(pp)) {
+              if (its == 0) status = isfinite(pp) ? GADI_ENOTSPD : overflow_status;
+              break;
+            }
+            const AT ak = (AT)(gam / pp);
+            // y += a_k p_k, r_{k+1} = r_k - a_k (I + S/alpha) p_k
+            double s0 = 0.0;
+            struct O {
+              ST y;
+              VT r;
+            };
+            auto store = [&](unsigned row, const O& o) {
+              at(wsol, row) = o.y;
+              at(R0, row) = o.r;
+              const double dr = (double)ld<AT>(o.r);
+              s0 += dr * dr;
+            };
+            if (its == 0) {
+              for_rows<BLOCK, U>(
+                  t0, t1,
+                  [&](unsigned row) {
+                    struct {
+                      VT p, r;
+                      decltype(pat.gather(0u, sv, gp)) g;
+                    } l{at(P, row), at(R0, row), pat.gather(row, sv, gp)};
+                    return l;
+                  },
+                  [&](const auto& l) {
+                    const AT pi = ldv(l.p);
+                    const AT v = pi + inv_alpha * pat.template dot<AT>(l.g, ldv);
+                    return O{(ST)(ak * pi), st<VT>(ldv(l.r) - ak * v)};
+                  },
+                  store);
+            } else {
+              for_rows<BLOCK, U>(
+                  t0, t1,
+                  [&](unsigned row) {
+                    struct {
+                      VT p, r;
+                      ST y;
+                      decltype(pat.gather(0u, sv, gp)) g;
+                    } l{at(P, row), at(R0, row), at(wsol, row), pat.gather(row, sv, gp)};
+                    return l;
+                  },
+                  [&](const auto& l) {
+                    const AT pi = ldv(l.p);
+                    const AT v = pi + inv_alpha * pat.template dot<AT>(l.g, ldv);
+                    return O{l.y + (ST)(ak * pi), st<VT>(ldv(l.r) - ak * v)};
+                  },
+                  store);
+            }
+            ALLREDUCE_P(7, s0, 0.0, 0.0, 0.0);
+            const double gnew = out[0];
+            ++its;
+            if (gnew <= eps_s2 * gs0 || its >= a.maxit_in || !isfinite(gnew)) break;
+            const AT beta = (AT)(gnew / gam);
+            gam = gnew;
+            // p_{k+1} = (I - S/alpha) r_{k+1} + beta_k p_k
+            double s1 = 0.0;
+            for_rows<BLOCK, U>(
+                t0, t1,
+                [&](unsigned row) {
+                  struct {
+                    VT r, p;
+                    decltype(pat.gather(0u, sv, gr0)) g;
+                  } l{at(R0, row), at(P, row), pat.gather(row, sv, gr0)};
+                  return l;
+                },
+                [&](const auto& l) {
+                  const AT ri = ldv(l.r);
+                  return st<VT>(ri - inv_alpha * pat.template dot<AT>(l.g, ldv) + beta * ldv(l.p));
+                },
+                [&](unsigned row, VT pn) {
+                  at(P, row) = pn;
+                  const double dp = (double)ld<AT>(pn);
+                  s1 += dp * dp;
+                });
+            ALLREDUCE_P(5, s1, 0.0, 0.0, 0.0);
+            pp = out[0];
+          }
+        }
+      } else if constexpr (FORM == 1) {
         // r_0 = g, t = (S/alpha) g
         {
           struct O {
@@ -708,8 +987,8 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
               [&](unsigned row) {
                 struct {
                   ST z;
-                  decltype(pat.gather(0u, soff, gz)) g;
-                } l{at(z, row), pat.gather(row, soff, gz)};
+                  decltype(pat.gather(0u, sv, gz)) g;
+                } l{at(z, row), pat.gather(row, sv, gz)};
                 return l;
               },
               [&](const auto& l) { return O{g_of(l.z), inv_alpha * pat.template dot<AT>(l.g, g_of)}; },
@@ -732,8 +1011,8 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
               [&](unsigned row) {
                 struct {
                   VT r;
-                  decltype(pat.gather(0u, soff, gT)) g;
-                } l{at(R0, row), pat.gather(row, soff, gT)};
+                  decltype(pat.gather(0u, sv, gT)) g;
+                } l{at(R0, row), pat.gather(row, sv, gT)};
                 return l;
               },
               [&](const auto& l) {
@@ -786,8 +1065,8 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                   [&](unsigned row) {
                     struct {
                       VT r, w;
-                      decltype(pat.gather(0u, soff, gl)) g;
-                    } l{at(rk, row), at(wk, row), pat.gather(row, soff, gl)};
+                      decltype(pat.gather(0u, sv, gl)) g;
+                    } l{at(rk, row), at(wk, row), pat.gather(row, sv, gl)};
                     return l;
                   },
                   [&](const auto& l) {
@@ -812,8 +1091,8 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                     struct {
                       VT r, w, sp, p;
                       ST ws;
-                      decltype(pat.gather(0u, soff, gl)) g;
-                    } l{at(rk, row), at(wk, row), at(sprev, row), at(P, row), at(wsol, row), pat.gather(row, soff, gl)};
+                      decltype(pat.gather(0u, sv, gl)) g;
+                    } l{at(rk, row), at(wk, row), at(sprev, row), at(P, row), at(wsol, row), pat.gather(row, sv, gl)};
                     return l;
                   },
                   [&](const auto& l) {
@@ -845,8 +1124,8 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                   [&](unsigned row) {
                     struct {
                       VT r;
-                      decltype(pat.gather(0u, soff, gT)) g;
-                    } l{at(rnew, row), pat.gather(row, soff, gT)};
+                      decltype(pat.gather(0u, sv, gT)) g;
+                    } l{at(rnew, row), pat.gather(row, sv, gT)};
                     return l;
                   },
                   [&](const auto& l) {
@@ -879,8 +1158,8 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
               [&](unsigned row) {
                 struct {
                   ST z;
-                  decltype(pat.gather(0u, soff, gz)) g;
-                } l{at(z, row), pat.gather(row, soff, gz)};
+                  decltype(pat.gather(0u, sv, gz)) g;
+                } l{at(z, row), pat.gather(row, sv, gz)};
                 return l;
               },
               [&](const auto& l) {
@@ -917,8 +1196,8 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                   [&](unsigned row) {
                     struct {
                       VT p;
-                      decltype(pat.gather(0u, soff, gvt)) g;
-                    } l{at(vp, row), pat.gather(row, soff, gvt)};
+                      decltype(pat.gather(0u, sv, gvt)) g;
+                    } l{at(vp, row), pat.gather(row, sv, gvt)};
                     return l;
                   },
                   [&](const auto& l) {
@@ -983,8 +1262,8 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                   [&](unsigned row) {
                     struct {
                       VT r, t, p;
-                      decltype(pat.gather(0u, soff, gvr)) g;
-                    } l{at(vr, row), at(vt, row), at(vp, row), pat.gather(row, soff, gvr)};
+                      decltype(pat.gather(0u, sv, gvr)) g;
+                    } l{at(vr, row), at(vt, row), at(vp, row), pat.gather(row, sv, gvr)};
                     return l;
                   },
                   [&](const auto& l) {
@@ -1004,7 +1283,24 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
       if (status != GADI_EMAXIT) break;
 
       // ---------------------------------------------------------- a6: x += (I - S/alpha) w * 2^(e1+e2)
-      if (its > 0) {
+      if constexpr (FORM >= 2) {
+        if (its > 0) {
+          // Craig's iterate is already (I - S/alpha) w
+          const double unscale = ldexp(1.0, e1 + e2);
+          for_rows<BLOCK, U>(
+              t0, t1,
+              [&](unsigned row) {
+                struct {
+                  ST y;
+                  XT x;
+                } l{at(wsol, row), at(x, row)};
+                return l;
+              },
+              [&](const auto& l) { return (XT)(l.x + (XT)((double)(AT)l.y * unscale)); },
+              [&](unsigned row, XT xn) { at(x, row) = xn; });
+          ALLREDUCE_P(8, 0.0, 0.0, 0.0, 0.0);
+        }
+      } else if (its > 0) {
         const double unscale = ldexp(1.0, e1 + e2);
         auto gw = [&](unsigned c) { return at(wsol, c); };
         for_rows<BLOCK, U>(
@@ -1013,8 +1309,8 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
               struct {
                 ST w;
                 XT x;
-                decltype(pat.gather(0u, soff, gw)) g;
-              } l{at(wsol, row), at(x, row), pat.gather(row, soff, gw)};
+                decltype(pat.gather(0u, sv, gw)) g;
+              } l{at(wsol, row), at(x, row), pat.gather(row, sv, gw)};
               return l;
             },
             [&](const auto& l) {

@@ -8,18 +8,22 @@
 namespace gadi {
 
 int num_cus();
+// GADI_SOLVE_PATTERN=generic: read the per-slice layout metadata even where
+// the uniform offsets allow the mirrored diagonal pattern
+bool generic_pattern_forced();
 
 // One large system: persistent cooperative launch, one band of rows per block.
 // PW = 0: per-slice layout metadata; PW = 4 or 6: uniformly diagonal-style
-// layout with PW offsets per slice (SolveArgs::dia_u).
-template <class Mode, int BLOCK, bool FUSED, int PW>
+// layout with PW offsets per slice (SolveArgs::dia_u), a set symmetric about
+// zero; H and S are read from their half layout (SolveArgs::h_half).
+template <class Mode, int BLOCK, int FORM, int PW>
 __global__ void __launch_bounds__(BLOCK) solve_kernel(SolveArgs a) {
   const long long t_begin = wall_clock64();
   GridRed<BLOCK> red{Grid{a.sync, a.flags, a.part, a.result, gridDim.x, 0ull, a.timeout, 0ll}};
-  if (a.barrier == 1) {
+  if (a.barrier != 0) {
     // XCC-hierarchical barrier: every block counts itself in the XCC that runs
     // it; after one relay barrier every block knows its XCC's block count and
-    // block 0 the XCCs in use
+    // the XCCs in use
     __shared__ unsigned sh_x[3];
     if (threadIdx.x == 0) {
       const unsigned x = current_xcc();
@@ -37,7 +41,7 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(SolveArgs a) {
       sh_x[2] = mask;
     }
     __syncthreads();
-    red.g.kind = 1;
+    red.g.kind = a.barrier;
     red.g.xcc = sh_x[0];
     red.g.xcc_n = sh_x[1];
     red.g.xcc_mask = sh_x[2];
@@ -52,13 +56,14 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(SolveArgs a) {
   if constexpr (PW == 0) {
     // per-slice metadata: a row's loads depend on loaded metadata, one tile at a time
     const PatGeneric pat{Pattern{a.slice_ptr, a.col, a.slice_dia, a.dia_off, a.n - 1}};
-    ok = solve_body<Mode, BLOCK, FUSED, 1>(a, red, pat, t0, t1, r);
+    ok = solve_body<Mode, BLOCK, FORM, 1>(a, red, pat, t0, t1, r);
   } else {
-    PatDia<PW> pat;
+    PatDiaSym<PW> pat;
 #pragma unroll
     for (int j = 0; j < PW; ++j) pat.off[j] = a.dia_u[j];
     pat.nmax = a.n - 1;
-    ok = solve_body<Mode, BLOCK, FUSED, Mode::tiles>(a, red, pat, t0, t1, r);
+    pat.pad = a.half_pad;
+    ok = solve_body<Mode, BLOCK, FORM, Mode::tiles>(a, red, pat, t0, t1, r);
   }
   if (!ok) return;
   // per-block profile: ticks inside barriers and in the whole launch
@@ -92,10 +97,10 @@ static __global__ void reset_sync_kernel(SyncState* s, unsigned long long* flags
   }
 }
 
-template <class Mode, int BLOCK, bool FUSED, int PW>
+template <class Mode, int BLOCK, int FORM, int PW>
 static gadi_status launch_t(System& s, SolveArgs a, int per_cu) {
   int nb = 0;
-  GADI_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, solve_kernel<Mode, BLOCK, FUSED, PW>, BLOCK, 0));
+  GADI_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, solve_kernel<Mode, BLOCK, FORM, PW>, BLOCK, 0));
   if (nb < 1 || per_cu > nb) return GADI_EINVAL;  // not co-resident: not a valid shape
   const int ntiles = s.npad / BLOCK;
   long long G = (long long)per_cu * num_cus();
@@ -106,42 +111,48 @@ static gadi_status launch_t(System& s, SolveArgs a, int per_cu) {
   hipLaunchKernelGGL(reset_sync_kernel, dim3(32), dim3(1024), 0, s.stream, a.sync, a.flags, a.info, a.prof);
   GADI_HIP_CHECK(hipGetLastError());
   void* kargs[] = {(void*)&a};
-  GADI_HIP_CHECK(hipLaunchCooperativeKernel((const void*)solve_kernel<Mode, BLOCK, FUSED, PW>, dim3((unsigned)G), dim3(BLOCK),
+  GADI_HIP_CHECK(hipLaunchCooperativeKernel((const void*)solve_kernel<Mode, BLOCK, FORM, PW>, dim3((unsigned)G), dim3(BLOCK),
                                             kargs, 0, s.stream));
   s.last_blocks = (int)G;
   s.last_block_threads = BLOCK;
   return GADI_OK;
 }
 
-template <class Mode, bool FUSED, int PW>
+template <class Mode, int FORM, int PW>
 static gadi_status launch_block(System& s, const SolveArgs& a, int block, int per_cu) {
   switch (block) {
     case 512:
       // the precision-study modes are built in one block size only
       if constexpr (Mode::id <= GADI_PREC_FP32_IR || Mode::id == GADI_PREC_FP8_IR)
-        return launch_t<Mode, 512, FUSED, PW>(s, a, per_cu);
+        return launch_t<Mode, 512, FORM, PW>(s, a, per_cu);
       return GADI_EINVAL;
-    case 1024: return launch_t<Mode, 1024, FUSED, PW>(s, a, per_cu);
+    case 1024: return launch_t<Mode, 1024, FORM, PW>(s, a, per_cu);
   }
   return GADI_EINVAL;
 }
 
-template <class Mode, bool FUSED>
+template <class Mode, int FORM>
 gadi_status launch_mode(System& s, const SolveArgs& a, int block, int per_cu) {
-  switch (s.dia_uniform) {
-    case 4: return launch_block<Mode, FUSED, 4>(s, a, block, per_cu);
-    case 6: return launch_block<Mode, FUSED, 6>(s, a, block, per_cu);
+  const bool half = s.dia_sym && a.h_half && a.s_half && !generic_pattern_forced();
+  switch (half ? s.dia_uniform : 0) {
+    case 4: return launch_block<Mode, FORM, 4>(s, a, block, per_cu);
+    case 6: return launch_block<Mode, FORM, 6>(s, a, block, per_cu);
   }
-  return launch_block<Mode, FUSED, 0>(s, a, block, per_cu);
+  return launch_block<Mode, FORM, 0>(s, a, block, per_cu);
 }
 
-// one explicit instantiation per mode and inner-solver form, each in its own
-// translation unit
-#define GADI_DECLARE_MODE(M)                                                                  \
-  extern template gadi_status launch_mode<M, true>(System&, const SolveArgs&, int, int);  \
-  extern template gadi_status launch_mode<M, false>(System&, const SolveArgs&, int, int);
-#define GADI_INSTANTIATE_MODE(M)                                                      \
-  template gadi_status launch_mode<M, true>(System&, const SolveArgs&, int, int);  \
-  template gadi_status launch_mode<M, false>(System&, const SolveArgs&, int, int);
+// one explicit instantiation per mode and inner-solver form (0 Hestenes-Stiefel,
+// 1 Chronopoulos-Gear, 2 pipelined CG with Craig's CGNE, 3 Hestenes-Stiefel CG
+// with Craig's CGNE), each mode in its own translation unit
+#define GADI_DECLARE_MODE(M)                                                          \
+  extern template gadi_status launch_mode<M, 0>(System&, const SolveArgs&, int, int); \
+  extern template gadi_status launch_mode<M, 1>(System&, const SolveArgs&, int, int); \
+  extern template gadi_status launch_mode<M, 2>(System&, const SolveArgs&, int, int); \
+  extern template gadi_status launch_mode<M, 3>(System&, const SolveArgs&, int, int);
+#define GADI_INSTANTIATE_MODE(M)                                               \
+  template gadi_status launch_mode<M, 0>(System&, const SolveArgs&, int, int); \
+  template gadi_status launch_mode<M, 1>(System&, const SolveArgs&, int, int); \
+  template gadi_status launch_mode<M, 2>(System&, const SolveArgs&, int, int); \
+  template gadi_status launch_mode<M, 3>(System&, const SolveArgs&, int, int);
 
 }  // namespace gadi

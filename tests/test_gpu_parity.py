@@ -311,19 +311,28 @@ def test_fp16_regularisation_grid(alpha, omega):
     assert np.linalg.norm(b - o.spmv("A", x)) <= 1.0000001e-10 * np.linalg.norm(b)
 
 
+@pytest.mark.parametrize("form", [0, 1, 2, 3])
 @pytest.mark.parametrize("prec", ["fp16", "h-d-s", "h-s-s", "fp8"])
-def test_fp16_small_alpha_fails_cleanly_where_fp32_continues(prec):
+def test_fp16_small_alpha_fails_cleanly_where_fp32_continues(prec, form, monkeypatch):
     """Too little regularisation: with alpha = 1e-3 the normal operator I - S^2/alpha^2 of the
-    S-step exceeds the half range (||S||/alpha ~ 3.5e3 here); every mode that stores its Krylov
-    vectors in half (fp16, h-d-s, h-s-s, fp8) stops with EOVERFLOW16 and a finite iterate, while
-    single precision keeps reducing the residual (cf. the paper's Table 3d, where half-precision
-    inner solves fail at the smallest alpha)."""
+    S-step exceeds the half range (||S||/alpha ~ 3.5e3 here).  The forms that apply it as one
+    operator (0 and 1: (S/alpha)^2-sized intermediates) stop, in every mode that stores its Krylov
+    vectors in half (fp16, h-d-s, h-s-s, fp8), with EOVERFLOW16 and a finite iterate (cf. the
+    paper's Table 3d, where half-precision inner solves fail at the smallest alpha).  Craig's
+    CGNE (forms 2 and 3) applies I + S/alpha and I - S/alpha separately, so its intermediates stay near
+    ||S||/alpha, inside the half range: it runs into the sweep limit like single precision, with a
+    finite iterate.  Single precision keeps reducing the residual."""
+    monkeypatch.setenv("GADI_SOLVE_FORM", str(form))
     A = gi.convdiff(16, 3, 20.0)
     g = gadi.System(A)
     o = oracle.OracleSystem(A)
     xs, b = gi.rhs_for(A, "uniform", 1)
-    x, info = g.solve(b, 1e-3, 0.5, tol=1e-10, prec=prec, maxit_outer=5)
-    assert info["status"] == gadi.EOVERFLOW16, info
+    x, info = g.solve(b, 1e-3, 0.5, tol=1e-10, prec=prec, maxit_outer=5, maxit_inner=500)
+    assert g.solver_form() == form
+    if form >= 2:
+        assert info["status"] == gadi.EMAXIT and info["outer_sweeps"] == 5, info
+    else:
+        assert info["status"] == gadi.EOVERFLOW16, info
     assert np.all(np.isfinite(x))
     x, info = g.solve(b, 1e-3, 0.5, tol=1e-10, prec="fp32", maxit_outer=5, maxit_inner=500)
     assert info["status"] == gadi.EMAXIT and info["outer_sweeps"] == 5, info
