@@ -508,7 +508,7 @@ __device__ __forceinline__ bool unit_body(const BArgs& ba, GroupSync<BLOCK>& gs,
             const VT* spp = (const VT*)vec(S0 + 1 - rk, t);
             const VT r_ = at(rkp, row), w_ = at(wkp, row);
             VT sp_{}, p_{};
-            ST z_{};
+            ST z_ = st<ST>(AT(0));
             VT nr[W], nw[W], ns[W];
 #pragma unroll
             for (int j = 0; j < W; ++j) {
@@ -529,11 +529,11 @@ __device__ __forceinline__ bool unit_body(const BArgs& ba, GroupSync<BLOCK>& gs,
             if (first) {
               s = ldv(w_);
               p = ri;
-              z = (ST)(akt * ri);
+              z = st<ST>(akt * ri);
             } else {
               s = rnd(fma_at<AT>(bkt, ldv(sp_), ldv(w_)));
               p = rnd(fma_at<AT>(bkt, ldv(p_), ri));
-              z = z_ + (ST)(akt * p);
+              z = st<ST>(ld<AT>(z_) + akt * p);
             }
             const AT rn = rnd(fma_at<AT>(-akt, s, ri));
             // r_{k+1} at the neighbouring rows, computed as their owners compute it
@@ -549,7 +549,7 @@ __device__ __forceinline__ bool unit_body(const BArgs& ba, GroupSync<BLOCK>& gs,
             at((VT*)vec(W0 + 1 - rk, t), row) = st<VT>(wn);
             red[3 * t] += (double)rn * (double)rn;
             red[3 * t + 1] += (double)wn * (double)rn;
-            red[3 * kPack + t] = fmax(red[3 * kPack + t], fabs((double)z));
+            red[3 * kPack + t] = fmax(red[3 * kPack + t], fabs((double)ld<AT>(z)));
           });
       });
       if (!gs.reduce(red)) return false;
@@ -609,9 +609,9 @@ __device__ __forceinline__ bool unit_body(const BArgs& ba, GroupSync<BLOCK>& gs,
 #pragma unroll
               for (int j = 0; j < W; ++j) zn[j] = at(zt, rv.c[j]);
               fence();
-              const AT g = rnd(U.tmo[t] * (AT)zo * U.sc[t]);
+              const AT g = rnd(U.tmo[t] * ld<AT>(zo) * U.sc[t]);
               const AT tv = U.inv_alpha[t] * rdot<AT>(rv, [&](int j, unsigned) {
-                              return rnd(U.tmo[t] * (AT)zn[j] * U.sc[t]);
+                              return rnd(U.tmo[t] * ld<AT>(zn[j]) * U.sc[t]);
                             });
               at((VT*)vec(R0, t), row) = st<VT>(g);
               at((VT*)vec(TV, t), row) = st<VT>(tv);
@@ -690,7 +690,7 @@ __device__ __forceinline__ bool unit_body(const BArgs& ba, GroupSync<BLOCK>& gs,
               const VT* spp = (const VT*)vec(S0 + 1 - rk, t);
               const VT r_ = at(rkp, row), w_ = at(wkp, row);
               VT sp_{}, p_{};
-              ST ws_{};
+              ST ws_ = st<ST>(AT(0));
               VT nr[W], nw[W], ns[W];
 #pragma unroll
               for (int j = 0; j < W; ++j) {
@@ -711,11 +711,11 @@ __device__ __forceinline__ bool unit_body(const BArgs& ba, GroupSync<BLOCK>& gs,
               if (first) {
                 s = ldv(w_);
                 p = ri;
-                wv = (ST)(akt * ri);
+                wv = st<ST>(akt * ri);
               } else {
                 s = rnd(fma_at<AT>(bkt, ldv(sp_), ldv(w_)));
                 p = rnd(fma_at<AT>(bkt, ldv(p_), ri));
-                wv = ws_ + (ST)(akt * p);
+                wv = st<ST>(ld<AT>(ws_) + akt * p);
               }
               const AT rn = rnd(fma_at<AT>(-akt, s, ri));
               const AT tv = U.inv_alpha[t] * rdot<AT>(rv, [&](int j, unsigned) {
@@ -802,7 +802,7 @@ __device__ __forceinline__ bool unit_body(const BArgs& ba, GroupSync<BLOCK>& gs,
 #pragma unroll
             for (int j = 0; j < W; ++j) wn[j] = at(wt, rv.c[j]);
             fence();
-            const AT ui = (AT)wo - U.inv_alpha[t] * rdot<AT>(rv, [&](int j, unsigned) { return (AT)wn[j]; });
+            const AT ui = ld<AT>(wo) - U.inv_alpha[t] * rdot<AT>(rv, [&](int j, unsigned) { return ld<AT>(wn[j]); });
             at((XT*)vec(X, t), row) = (XT)(xo + (XT)((double)ui * U.unscale[t]));
           });
       });

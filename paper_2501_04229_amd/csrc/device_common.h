@@ -23,7 +23,7 @@ struct ModeF16 {  // (half, double, double)
   using MT = __half;
   using DT = __half;
   using VT = __half;
-  using ST = float;
+  using ST = __half;
   using RT = float;
   using AT = float;
   using XT = double;

@@ -583,7 +583,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
               at(wnew, row) = st<VT>(o.wn);
               g1 += (double)o.rn * (double)o.rn;
               d1 += (double)o.wn * (double)o.rn;
-              m3 = fmax(m3, fabs((double)o.z));
+              m3 = fmax(m3, fabs((double)ld<AT>(o.z)));
             };
             if (k == 0) {
               // s_0 = w_0, p_0 = r_0; r_1 at row c = r_0 - a_0 w_0
@@ -604,7 +604,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                     const AT ri = ldv(l.r);
                     o.s = ldv(l.w);
                     o.p = ri;
-                    o.z = (ST)(akt * ri);
+                    o.z = st<ST>(akt * ri);
                     o.rn = rnd(fma_at<AT>(-akt, o.s, ri));
                     o.wn = rnd((alpha + ld<AT>(l.hd)) * o.rn + pat.template dot<AT>(l.g, r_next));
                     return o;
@@ -633,7 +633,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                     const AT ri = ldv(l.r);
                     o.s = rnd(fma_at<AT>(bkt, ldv(l.sp), ldv(l.w)));
                     o.p = rnd(fma_at<AT>(bkt, ldv(l.p), ri));
-                    o.z = l.z + (ST)(akt * o.p);
+                    o.z = st<ST>(ld<AT>(l.z) + akt * o.p);
                     o.rn = rnd(fma_at<AT>(-akt, o.s, ri));
                     o.wn = rnd((alpha + ld<AT>(l.hd)) * o.rn + pat.template dot<AT>(l.g, r_next));
                     return o;
@@ -658,7 +658,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
               at(wnew, row) = st<VT>(o.wn);
               g1 += (double)o.rn * (double)o.rn;
               d1 += (double)o.wn * (double)o.rn;
-              m3 = fmax(m3, fabs((double)o.z));
+              m3 = fmax(m3, fabs((double)ld<AT>(o.z)));
             };
             if (k == 0) {
               // u_0 = K w_0, s_0 = w_0, p_0 = r_0
@@ -678,7 +678,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                     o.u = rnd((alpha + ld<AT>(l.hd)) * wi + pat.template dot<AT>(l.g, ldv));
                     o.s = wi;
                     o.p = ri;
-                    o.z = (ST)(akt * ri);
+                    o.z = st<ST>(akt * ri);
                     o.rn = rnd(fma_at<AT>(-akt, o.s, ri));
                     o.wn = rnd(fma_at<AT>(-akt, o.u, wi));
                     return o;
@@ -704,7 +704,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                     o.u = rnd(fma_at<AT>(bkt, ldv(l.u), kw));
                     o.s = rnd(fma_at<AT>(bkt, ldv(l.s), wi));
                     o.p = rnd(fma_at<AT>(bkt, ldv(l.p), ri));
-                    o.z = l.z + (ST)(akt * o.p);
+                    o.z = st<ST>(ld<AT>(l.z) + akt * o.p);
                     o.rn = rnd(fma_at<AT>(-akt, o.s, ri));
                     o.wn = rnd(fma_at<AT>(-akt, o.u, wi));
                     return o;
@@ -781,14 +781,14 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                   struct {
                     VT p, r, q;
                     ST z;
-                  } l{at(vp, row), at(vr, row), at(vq, row), FIRST ? ST(0) : at(z, row)};
+                  } l{at(vp, row), at(vr, row), at(vq, row), FIRST ? st<ST>(AT(0)) : at(z, row)};
                   return l;
                 },
                 [&](const auto& l) {
                   const AT pi = ldv(l.p);
                   O o;
-                  if constexpr (FIRST) o.z = (ST)(ak * pi);
-                  else o.z = l.z + (ST)(ak * pi);
+                  if constexpr (FIRST) o.z = st<ST>(ak * pi);
+                  else o.z = st<ST>(ld<AT>(l.z) + ak * pi);
                   o.r = st<VT>(ldv(l.r) - ak * ldv(l.q));
                   return o;
                 },
@@ -797,7 +797,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                   at(vr, row) = o.r;
                   const double dr = (double)ld<AT>(o.r);
                   s0 += dr * dr;
-                  m3 = fmax(m3, fabs((double)o.z));
+                  m3 = fmax(m3, fabs((double)ld<AT>(o.z)));
                 });
           });
           ALLREDUCE_P(3, s0, 0.0, 0.0, m3);
@@ -854,7 +854,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
       e2 = clamp_exp(e2);
       const AT sc2 = (AT)ldexp(1.0, -e2);
       // g = (2 - omega) z 2^-e2 rounded to the storage type, from a loaded z
-      auto g_of = [&](ST zc) { return rnd(two_m_omega * (AT)zc * sc2); };
+      auto g_of = [&](ST zc) { return rnd(two_m_omega * ld<AT>(zc) * sc2); };
       auto gz = [&](unsigned c) { return at(z, c); };
       auto gT = [&](unsigned c) { return at(T, c); };
       if constexpr (FORM >= 2) {
@@ -924,7 +924,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                   [&](const auto& l) {
                     const AT pi = ldv(l.p);
                     const AT v = pi + inv_alpha * pat.template dot<AT>(l.g, ldv);
-                    return O{(ST)(ak * pi), st<VT>(ldv(l.r) - ak * v)};
+                    return O{st<ST>(ak * pi), st<VT>(ldv(l.r) - ak * v)};
                   },
                   store);
             } else {
@@ -941,7 +941,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                   [&](const auto& l) {
                     const AT pi = ldv(l.p);
                     const AT v = pi + inv_alpha * pat.template dot<AT>(l.g, ldv);
-                    return O{l.y + (ST)(ak * pi), st<VT>(ldv(l.r) - ak * v)};
+                    return O{st<ST>(ld<AT>(l.y) + ak * pi), st<VT>(ldv(l.r) - ak * v)};
                   },
                   store);
             }
@@ -1074,7 +1074,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                     const AT ri = ldv(l.r);
                     o.s = ldv(l.w);
                     o.p = ri;
-                    o.w = (ST)(akt * ri);
+                    o.w = st<ST>(akt * ri);
                     o.rn = rnd(fma_at<AT>(-akt, o.s, ri));
                     o.t = inv_alpha * pat.template dot<AT>(l.g, r_next);
                     return o;
@@ -1100,7 +1100,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                     const AT ri = ldv(l.r);
                     o.s = rnd(fma_at<AT>(bkt, ldv(l.sp), ldv(l.w)));
                     o.p = rnd(fma_at<AT>(bkt, ldv(l.p), ri));
-                    o.w = l.ws + (ST)(akt * o.p);
+                    o.w = st<ST>(ld<AT>(l.ws) + akt * o.p);
                     o.rn = rnd(fma_at<AT>(-akt, o.s, ri));
                     o.t = inv_alpha * pat.template dot<AT>(l.g, r_next);
                     return o;
@@ -1163,9 +1163,9 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                 return l;
               },
               [&](const auto& l) {
-                const VT gi = st<VT>(two_m_omega * (AT)l.z * sc2);
+                const VT gi = st<VT>(two_m_omega * ld<AT>(l.z) * sc2);
                 const AT tv = inv_alpha * pat.template dot<AT>(l.g, [&](ST zc) {
-                                return ld<AT>(st<VT>(two_m_omega * (AT)zc * sc2));
+                                return ld<AT>(st<VT>(two_m_omega * ld<AT>(zc) * sc2));
                               });
                 return O{gi, st<VT>(tv)};
               },
@@ -1229,14 +1229,14 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                     struct {
                       VT p, r, q;
                       ST w;
-                    } l{at(vp, row), at(vr, row), at(vq, row), FIRST ? ST(0) : at(w, row)};
+                    } l{at(vp, row), at(vr, row), at(vq, row), FIRST ? st<ST>(AT(0)) : at(w, row)};
                     return l;
                   },
                   [&](const auto& l) {
                     const AT pi = ldv(l.p);
                     O o;
-                    if constexpr (FIRST) o.w = (ST)(ak * pi);
-                    else o.w = l.w + (ST)(ak * pi);
+                    if constexpr (FIRST) o.w = st<ST>(ak * pi);
+                    else o.w = st<ST>(ld<AT>(l.w) + ak * pi);
                     o.r = st<VT>(ldv(l.r) - ak * ldv(l.q));
                     return o;
                   },
@@ -1296,7 +1296,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                 } l{at(wsol, row), at(x, row)};
                 return l;
               },
-              [&](const auto& l) { return (XT)(l.x + (XT)((double)(AT)l.y * unscale)); },
+              [&](const auto& l) { return (XT)(l.x + (XT)((double)ld<AT>(l.y) * unscale)); },
               [&](unsigned row, XT xn) { at(x, row) = xn; });
           ALLREDUCE_P(8, 0.0, 0.0, 0.0, 0.0);
         }
@@ -1314,7 +1314,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
               return l;
             },
             [&](const auto& l) {
-              const AT ui = (AT)l.w - inv_alpha * pat.template dot<AT>(l.g, [](ST v) { return (AT)v; });
+              const AT ui = ld<AT>(l.w) - inv_alpha * pat.template dot<AT>(l.g, [](ST v) { return ld<AT>(v); });
               // the update in the solution precision u
               return (XT)(l.x + (XT)((double)ui * unscale));
             },

@@ -37,10 +37,10 @@ def family():
 
 @pytest.mark.parametrize("prec", ["fp16", "fp64"])
 def test_batched_matches_single_solves(family, prec, monkeypatch):
-    """The batched kernel runs the Hestenes-Stiefel inner form; the single solves are pinned to the
-    same form, so that failure statuses (the half overflow of I - (S/alpha)^2 at small alpha,
+    """The batched kernel runs the Chronopoulos-Gear inner form; the single solves are pinned to
+    the same form, so that failure statuses (the half overflow of I - (S/alpha)^2 at small alpha,
     which Craig's CGNE does not meet) agree trial by trial."""
-    monkeypatch.setenv("GADI_SOLVE_FORM", "0")
+    monkeypatch.setenv("GADI_SOLVE_FORM", "1")
     systems = [f[2] for f in family]
     bs = [f[1] for f in family]
     eps = 1e-6 if prec == "fp64" else None
