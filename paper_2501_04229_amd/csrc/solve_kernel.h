@@ -63,7 +63,9 @@ __global__ void __launch_bounds__(BLOCK) solve_kernel(SolveArgs a) {
     for (int j = 0; j < PW; ++j) pat.off[j] = a.dia_u[j];
     pat.nmax = a.n - 1;
     pat.pad = a.half_pad;
-    ok = solve_body<Mode, BLOCK, FORM, Mode::tiles>(a, red, pat, t0, t1, r);
+    // 512-thread blocks run 8 waves per compute unit with up to 256 registers
+    // each: twice the row tiles in flight per thread of the 1024-thread blocks
+    ok = solve_body<Mode, BLOCK, FORM, (BLOCK == 512 ? 2 * Mode::tiles : Mode::tiles)>(a, red, pat, t0, t1, r);
   }
   if (!ok) return;
   // per-block profile: ticks inside barriers and in the whole launch
