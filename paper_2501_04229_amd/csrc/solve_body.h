@@ -459,32 +459,89 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
     VT w, r;
   };
 
+  // forms 2, 3: x alternates between a.x and R1; a pending correction a6
+  [[maybe_unused]] XT* xcur = x;
+  [[maybe_unused]] XT* const xalt = (XT*)a.v[1];
+  [[maybe_unused]] bool pend = false;
+  [[maybe_unused]] double unscale_p = 0.0;
   for (;;) {
     // ---------------------------------------------------------- a1: residual
+    // Forms 2 and 3 apply the previous sweep's correction a6 here: each row's
+    // corrected x, and its neighbours' (recomputed with the same operations, so
+    // every copy is bit-identical), enter the residual, and the corrected x is
+    // written to the other x buffer (R1 of the Krylov vectors, unused by these
+    // forms): one phase fewer per sweep.
     {
       double s0 = 0.0, m3 = 0.0;
-      auto gx = [&](unsigned c) { return at(x, c); };
-      for_rows<BLOCK, U>(
-          t0, t1,
-          [&](unsigned row) {
-            struct {
-              AV d;
-              XT xr;
-              double br;
-              decltype(pat.gather(0u, aoff, gx)) g;
-            } l{at(adiag, row), at(x, row), at(b, row), pat.gather(row, aoff, gx)};
-            return l;
-          },
-          [&](const auto& l) {
-            // in the residual precision u_f (double unless a single-precision mode)
-            const FT ax = (FT)l.d * (FT)l.xr + pat.template dot<FT>(l.g, [](XT v) { return (FT)v; });
-            return (double)((FT)l.br - ax);
-          },
-          [&](unsigned row, double ri) {
-            at(r, row) = (RT)ri;
-            s0 += ri * ri;
-            m3 = fmax(m3, fabs(ri));
-          });
+      bool applied = false;
+      if constexpr (FORM >= 2) {
+        if (pend) {
+          struct XY {
+            XT x;
+            ST y;
+          };
+          struct RX {
+            double r;
+            XT x;
+          };
+          XT* __restrict__ xo = xcur;
+          XT* __restrict__ xn = xcur == x ? xalt : x;
+          const double us = unscale_p;
+          auto corr = [us](XT xv, ST yv) { return (XT)(xv + (XT)((double)ld<AT>(yv) * us)); };
+          auto gxy = [&](unsigned c) { return XY{at(xo, c), at(wsol, c)}; };
+          for_rows<BLOCK, U>(
+              t0, t1,
+              [&](unsigned row) {
+                struct {
+                  AV d;
+                  XY xy;
+                  double br;
+                  decltype(pat.gather(0u, aoff, gxy)) g;
+                } l{at(adiag, row), XY{at(xo, row), at(wsol, row)}, at(b, row), pat.gather(row, aoff, gxy)};
+                return l;
+              },
+              [&](const auto& l) {
+                const XT xr = corr(l.xy.x, l.xy.y);
+                const FT ax = (FT)l.d * (FT)xr +
+                              pat.template dot<FT>(l.g, [&](const XY& v) { return (FT)corr(v.x, v.y); });
+                return RX{(double)((FT)l.br - ax), xr};
+              },
+              [&](unsigned row, const RX& o) {
+                at(r, row) = (RT)o.r;
+                at(xn, row) = o.x;
+                s0 += o.r * o.r;
+                m3 = fmax(m3, fabs(o.r));
+              });
+          xcur = xn;
+          pend = false;
+          applied = true;
+        }
+      }
+      if (!applied) {
+        XT* __restrict__ xr_ = xcur;
+        auto gx = [&](unsigned c) { return at(xr_, c); };
+        for_rows<BLOCK, U>(
+            t0, t1,
+            [&](unsigned row) {
+              struct {
+                AV d;
+                XT xr;
+                double br;
+                decltype(pat.gather(0u, aoff, gx)) g;
+              } l{at(adiag, row), at(xr_, row), at(b, row), pat.gather(row, aoff, gx)};
+              return l;
+            },
+            [&](const auto& l) {
+              // in the residual precision u_f (double unless a single-precision mode)
+              const FT ax = (FT)l.d * (FT)l.xr + pat.template dot<FT>(l.g, [](XT v) { return (FT)v; });
+              return (double)((FT)l.br - ax);
+            },
+            [&](unsigned row, double ri) {
+              at(r, row) = (RT)ri;
+              s0 += ri * ri;
+              m3 = fmax(m3, fabs(ri));
+            });
+      }
       ALLREDUCE_P(0, s0, 0.0, 0.0, m3);
     }
     const double rho = sqrt(out[0]);
@@ -1284,21 +1341,11 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
 
       // ---------------------------------------------------------- a6: x += (I - S/alpha) w * 2^(e1+e2)
       if constexpr (FORM >= 2) {
+        // Craig's iterate is already (I - S/alpha) w: x += y 2^(e1+e2) is
+        // applied by the next residual phase
         if (its > 0) {
-          // Craig's iterate is already (I - S/alpha) w
-          const double unscale = ldexp(1.0, e1 + e2);
-          for_rows<BLOCK, U>(
-              t0, t1,
-              [&](unsigned row) {
-                struct {
-                  ST y;
-                  XT x;
-                } l{at(wsol, row), at(x, row)};
-                return l;
-              },
-              [&](const auto& l) { return (XT)(l.x + (XT)((double)ld<AT>(l.y) * unscale)); },
-              [&](unsigned row, XT xn) { at(x, row) = xn; });
-          ALLREDUCE_P(8, 0.0, 0.0, 0.0, 0.0);
+          pend = true;
+          unscale_p = ldexp(1.0, e1 + e2);
         }
       } else if (its > 0) {
         const double unscale = ldexp(1.0, e1 + e2);
@@ -1325,6 +1372,13 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
     ++sweep;
   }
 
+  if constexpr (FORM >= 2) {
+    // the solution is wherever the last residual phase left it
+    if (xcur != x)
+      for_rows<BLOCK, U>(
+          t0, t1, [&](unsigned row) { return at(xalt, row); }, [](XT v) { return v; },
+          [&](unsigned row, XT v) { at(x, row) = v; });
+  }
   if (a.prune && status == GADI_OK)
     red.publish_min(a.prune, (unsigned long long)(ih + 2 * is + 5 * (long long)sweep));
   res_out.status = status;
