@@ -472,6 +472,8 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
     // written to the other x buffer (R1 of the Krylov vectors, unused by these
     // forms): one phase fewer per sweep.
     {
+      // the residual's double-precision rows hold the most loads: at most two tiles in flight
+      constexpr int UR = U > 2 ? 2 : U;
       double s0 = 0.0, m3 = 0.0;
       bool applied = false;
       if constexpr (FORM >= 2) {
@@ -489,7 +491,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
           const double us = unscale_p;
           auto corr = [us](XT xv, ST yv) { return (XT)(xv + (XT)((double)ld<AT>(yv) * us)); };
           auto gxy = [&](unsigned c) { return XY{at(xo, c), at(wsol, c)}; };
-          for_rows<BLOCK, U>(
+          for_rows<BLOCK, UR>(
               t0, t1,
               [&](unsigned row) {
                 struct {
@@ -520,7 +522,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
       if (!applied) {
         XT* __restrict__ xr_ = xcur;
         auto gx = [&](unsigned c) { return at(xr_, c); };
-        for_rows<BLOCK, U>(
+        for_rows<BLOCK, UR>(
             t0, t1,
             [&](unsigned row) {
               struct {
