@@ -42,7 +42,9 @@ typedef enum {
   GADI_EMAXIT = 5,      /* outer sweep limit reached */
   GADI_EHIP = 6,        /* a HIP runtime call failed */
   GADI_ENOMEM = 7,      /* host or device allocation failed */
-  GADI_EBARRIER = 8     /* a device-wide barrier timed out (the kernel bailed out) */
+  GADI_EBARRIER = 8,    /* a device-wide barrier timed out (the kernel bailed out) */
+  GADI_EPRUNED = 9      /* batched with prune_dominated only: the trial was stopped because its work
+                           exceeded that of a converged trial of the same system */
 } gadi_status;
 
 /* Square CSR matrix, int32 indices, float64 values, read-only and owned by the
@@ -92,10 +94,10 @@ typedef struct {
   int32_t maxit_inner;  /* per inner solve                                      */
   int32_t on_device;    /* 1: b and x are device pointers; 0: host pointers     */
   int32_t record_history; /* 1: keep RES per sweep, read with gadi_get_history  */
-  int32_t prune_dominated; /* batched only: a trial stops with EMAXIT once its work
-                              (operator products: CG steps + 2 CGNE steps + 3 per
-                              sweep) exceeds that of a converged trial of the same
-                              system; the best trial of every system is unaffected */
+  int32_t prune_dominated; /* batched only: a trial stops with GADI_EPRUNED once its
+                              work (phases: CG steps + 2 CGNE steps + 5 per sweep)
+                              exceeds that of a converged trial of the same system;
+                              the best trial of every system is unaffected */
   int32_t grid_per_system; /* batched only: alpha/omega hold nsys * ntrial values,
                               system-major (a separate trial grid per system) */
 } gadi_options;
@@ -179,9 +181,12 @@ int32_t gadi_get_history(gadi_handle* h, double* out, int32_t cap);
  * hs[nsys]: handles set up beforehand; b[s], x[s]: per-system host vectors
  * (x[s] receives the last iterate of trial 0 of system s and may be NULL);
  * alpha[t], omega[t] for t < ntrial (ntrial <= 16): the same trial grid for
- * every system, or alpha[s * ntrial + t] with opts->grid_per_system.  info[s * ntrial + t] receives each trial's record.  Trials
- * start from x_0 = 0.  The parameter sweep of the paper's training-set
- * generation (Section 3.3.2) uses this call. */
+ * every system, or alpha[s * ntrial + t] with opts->grid_per_system.
+ * info[s * ntrial + t] receives each trial's record (status GADI_EPRUNED for a
+ * trial stopped by opts->prune_dominated).  Trials start from x_0 = 0.  Returns
+ * GADI_OK, GADI_EMAXIT if some trial reached the sweep limit, or an error.  The
+ * parameter sweep of the paper's training-set generation (Section 3.3.2) uses
+ * this call. */
 gadi_status gadi_ir_solve_batched(gadi_handle* const* hs, int32_t nsys, const double* const* b,
                                   double* const* x, const double* alpha, const double* omega,
                                   int32_t ntrial, double tol, const gadi_options* opts,

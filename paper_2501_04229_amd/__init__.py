@@ -18,7 +18,7 @@ from . import build as _build
 
 LIB_PATH = _build.LIB
 
-OK, EINVAL, ENOTSPD, EOVERFLOW16, EDIVERGED, EMAXIT, EHIP, ENOMEM, EBARRIER = range(9)
+OK, EINVAL, ENOTSPD, EOVERFLOW16, EDIVERGED, EMAXIT, EHIP, ENOMEM, EBARRIER, EPRUNED = range(10)
 PREC = {"fp64": 0, "fp16": 1, "fp32": 2, "h-d-s": 3, "h-s-s": 4, "s-s-s": 5, "fp8": 6}
 N_MLP_PARAMS = 4866
 

@@ -419,7 +419,7 @@ __device__ __forceinline__ bool unit_body(const BArgs& ba, GroupSync<BLOCK>& gs,
         if (rho <= ba.tol * U.rho0[t]) stop = GADI_OK;
         else if (!isfinite(rho) || rho > 1e6 * U.rho0[t]) stop = GADI_EDIVERGED;
         else if (U.sweep[t] >= ba.maxit_out) stop = GADI_EMAXIT;
-        else if (ba.best_work && (double)wk > best) stop = GADI_EMAXIT;
+        else if (ba.best_work && (double)wk > best) stop = GADI_EPRUNED;
         if (stop >= 0) {
           U.status[t] = stop;
           U.live &= ~(1u << t);

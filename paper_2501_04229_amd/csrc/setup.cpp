@@ -376,6 +376,7 @@ extern "C" const char* gadi_status_str(gadi_status s) {
     case GADI_EHIP: return "HIP runtime error";
     case GADI_ENOMEM: return "out of memory";
     case GADI_EBARRIER: return "device barrier timed out";
+    case GADI_EPRUNED: return "pruned: dominated by a converged trial";
   }
   return "unknown status";
 }

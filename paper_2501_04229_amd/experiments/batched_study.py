@@ -78,7 +78,8 @@ def main():
         mat = sum(2.0 * (L["nnz_off"] + L["n"]) for L in lay) / max(1, sum(L["n"] for L in lay))
         res["groups"].append({"first": g0, "systems": len(systems), "rows": rows, "seconds": dt, "setup_s": t_setup,
                               "trials": len(flat), "converged": ok, "sweeps": sweeps,
-                              "maxit_or_pruned": sum(r["status"] == gadi.EMAXIT for r in flat),
+                              "maxit": sum(r["status"] == gadi.EMAXIT for r in flat),
+                              "pruned": sum(r["status"] == gadi.EPRUNED for r in flat),
                               "matrix_bytes_per_row_product_unshared": mat,
                               "matrix_bytes_per_row_product_per_trial": mat / 4.0,
                               "sweeps_per_s": sweeps / dt, "trials_per_s": len(flat) / dt,

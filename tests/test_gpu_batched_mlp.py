@@ -267,3 +267,32 @@ def test_solve_auto_rejects_a_prediction_slower_than_the_default():
     assert info["guard_seconds"] > 0
     x, info2, used2 = pr.solve_auto(g, A, b, p, tol=1e-10, judge="measure")
     assert used2 == "default" and info2["guard_seconds"] == 0.0
+
+
+def test_pruned_trials_carry_their_own_status(family):
+    """With prune_dominated, a trial whose work passes that of a converged trial of the same
+    system stops with EPRUNED (not EMAXIT): its work is above the least converged work of its
+    system, and every system's cheapest converged trial is the one an unpruned launch finds."""
+    from paper_2501_04229_amd import predictor as pr
+    systems = [f[2] for f in family]
+    bs = [f[1] for f in family]
+    alphas = [0.0215, 0.464, 2.0, 10.0, 0.1, 1.0, 5.0, 0.05]
+    omegas = [1.0, 0.5, 0.0, 1.5, 0.5, 1.0, 0.5, 0.0]
+    pruned, _ = gadi.solve_batched(systems, bs, alphas, omegas, tol=1e-10, prec="fp16", maxit_outer=4000,
+                                   prune=True)
+    full, _ = gadi.solve_batched(systems, bs, alphas, omegas, tol=1e-10, prec="fp16", maxit_outer=4000,
+                                 prune=False)
+    n_pruned = 0
+    for si in range(len(systems)):
+        ok_full = [pr.work(r) for r in full[si] if r["status"] == gadi.OK]
+        ok_pruned = [pr.work(r) for r in pruned[si] if r["status"] == gadi.OK]
+        if not ok_full:
+            continue
+        # the cheapest converged trial survives pruning, with the same work
+        assert min(ok_pruned) == min(ok_full), (si, ok_pruned, ok_full)
+        assert all(r["status"] != gadi.EPRUNED for r in full[si])
+        for r in pruned[si]:
+            if r["status"] == gadi.EPRUNED:
+                n_pruned += 1
+                assert pr.work(r) > min(ok_pruned), (si, r)
+    assert n_pruned > 0
