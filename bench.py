@@ -570,6 +570,13 @@ def main():
     out["roofline"]["traffic_source"] = tsrc
     if traffic:
         out["roofline"]["traffic_over_moved"] = traffic / (sm["moved_bytes"] / launches)
+        # measured HBM traffic (counters) over the measured launch time: the kernel's own HBM rate
+        out["roofline"]["traffic_GBs"] = traffic / launch_s / 1e9
+        out["roofline"]["traffic_frac"] = traffic / launch_s / 1e9 / HBM_PEAK_GBS
+    if achieved > HBM_PEAK_GBS:
+        out["roofline"]["frac_note"] = ("frac > 1: the CSR figures count a 4-byte column index per entry and every "
+                                        "value of H and S, which the packed diagonal layout and the half layout of "
+                                        "H and S never move; moved_frac and traffic_frac rate the bytes moved")
     if args.copy_calibration:
         xc = torch.ones(1 << 26, device="cuda", dtype=torch.float32)
         yc = torch.empty_like(xc)
