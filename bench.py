@@ -153,8 +153,9 @@ def _graph_time(fn, out, reps):
 
 def spmv_gbs(g, A, alpha, reps=50):
     """Stand-alone products: fp16 (alpha I + H) x moves 2 (z_o + N) + 4 z_e + 4 N
-    algorithmic bytes, fp64 A x moves 8 (z_o + N) + 4 z_e + 16 N.  Device time
-    per product from a replayed graph of reps products."""
+    algorithmic bytes in the packed layout (z_o + 6 N through the half layout of
+    a symmetric stencil pattern), fp64 A x moves 8 (z_o + N) + 4 z_e + 16 N.
+    Device time per product from a replayed graph of reps products."""
     import torch
     n = A.n
     gen = torch.Generator(device="cuda").manual_seed(5)
@@ -167,8 +168,15 @@ def spmv_gbs(g, A, alpha, reps=50):
     y64 = torch.empty_like(x64)
     dt64 = _graph_time(lambda: g.spmv("A", x64, y64), y64, reps)
     by64 = 8.0 * (L["nnz_off"] + n) + 4.0 * L["explicit_entries"] + 16.0 * n
-    return {"fp16_H_us": dt * 1e6, "fp16_H_GBs": by / dt / 1e9, "fp64_A_us": dt64 * 1e6,
-            "fp64_A_GBs": by64 / dt64 / 1e9, "timing": "graph of %d products, best of 3 replays" % reps}
+    out = {"fp16_H_us": dt * 1e6, "fp16_H_GBs": by / dt / 1e9, "fp64_A_us": dt64 * 1e6,
+           "fp64_A_GBs": by64 / dt64 / 1e9, "timing": "graph of %d products, best of 3 replays" % reps}
+    z = L["nnz_off"] + n
+    # the survey's CSR figure for the same product (2-byte value + 4-byte column per entry, 8 bytes per row)
+    out["fp16_H_csr_GBs"] = (6.0 * z + 8.0 * n) / dt / 1e9
+    if L["uniform_offsets"]:
+        # H read through its half layout: half of the off-diagonal values
+        out["fp16_H_half_layout_GBs"] = (1.0 * L["nnz_off"] + 6.0 * n) / dt / 1e9
+    return out
 
 
 def survey_bytes(prec: str, z: int, zs: int, n: int, sweeps: int, inner_h: int, inner_s: int,

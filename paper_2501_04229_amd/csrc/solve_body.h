@@ -204,7 +204,7 @@ struct PatDia {
   int off[W];
   int nmax;
   template <bool SKEW, class MT>
-  __device__ __forceinline__ const MT* mirror(const MT* p, const MT*) const {
+  __host__ __device__ __forceinline__ const MT* mirror(const MT* p, const MT*) const {
     return p;
   }
   template <class MT, class R>
@@ -271,7 +271,7 @@ struct PatDiaSym : PatDia<W> {
   int pad;  // zero rows in front of row 0 of the half layout (a multiple of kSlice, >= off[W-1])
   using PatDia<W>::gather;
   template <bool SKEW, class MT>
-  __device__ __forceinline__ MirrorVals<MT, SKEW> mirror(const MT*, const MT* half) const {
+  __host__ __device__ __forceinline__ MirrorVals<MT, SKEW> mirror(const MT*, const MT* half) const {
     return {half};
   }
   template <class MT, bool SKEW, class LD>
@@ -299,7 +299,7 @@ struct PatDiaSym : PatDia<W> {
 struct PatGeneric {
   Pattern p;
   template <bool SKEW, class MT>
-  __device__ __forceinline__ const MT* mirror(const MT* p, const MT*) const {
+  __host__ __device__ __forceinline__ const MT* mirror(const MT* p, const MT*) const {
     return p;
   }
   template <class MT, class LD>

@@ -8,6 +8,7 @@
 namespace gadi {
 
 gadi_status ensure_fp8_public(System& s);
+gadi_status ensure_half(System& s, int kind, const void* hfull, const void* sfull);
 
 // The products run the solver's row loop (solve_body.h): every load of U
 // tiles of BLOCK rows is issued before their arithmetic, under the same
@@ -41,10 +42,10 @@ __global__ void __launch_bounds__(kSpmvBlock) spmv_a64_kernel(Pat pat, const dou
       });
 }
 
-// y = (alpha I + H) x with H, x, y in the value type MT, arithmetic in AT
-// y = (alpha I + H) x: off-diagonal values MT, diagonal and vectors VT
-template <int U, class Pat, class MT, class VT, class AT>
-__global__ void __launch_bounds__(kSpmvBlock) spmv_h_kernel(Pat pat, const MT* __restrict__ off,
+// y = (alpha I + H) x: off-diagonal values (OV: a pointer to MT, or H's half
+// layout under PatDiaSym), diagonal and vectors VT, arithmetic in AT
+template <int U, class Pat, class OV, class VT, class AT>
+__global__ void __launch_bounds__(kSpmvBlock) spmv_h_kernel(Pat pat, OV off,
                                                            const VT* __restrict__ diag, const VT* __restrict__ x,
                                                            VT* __restrict__ y, AT alpha, int n, int ntiles) {
   const int t0 = blockIdx.x * U, t1 = t0 + U < ntiles ? t0 + U : ntiles;
@@ -66,9 +67,9 @@ __global__ void __launch_bounds__(kSpmvBlock) spmv_h_kernel(Pat pat, const MT* _
       });
 }
 
-// y = (I + S / alpha) x, half in/out, float arithmetic
-template <int U, class Pat>
-__global__ void __launch_bounds__(kSpmvBlock) spmv_s16_kernel(Pat pat, const __half* __restrict__ off,
+// y = (I + S / alpha) x, half in/out, float arithmetic (OV as above)
+template <int U, class Pat, class OV>
+__global__ void __launch_bounds__(kSpmvBlock) spmv_s16_kernel(Pat pat, OV off,
                                                              const __half* __restrict__ x, __half* __restrict__ y,
                                                              float inv_alpha, int n, int ntiles) {
   const int t0 = blockIdx.x * U, t1 = t0 + U < ntiles ? t0 + U : ntiles;
@@ -137,7 +138,9 @@ __global__ void __launch_bounds__(kRowBlock) gershgorin_kernel(const int32_t* __
 
 using namespace gadi;
 
-// U16 / U64: tiles per block of the half and double products
+// U16 / U64: tiles per block of the half and double products (4 and 2 on the
+// uniform layout: measured best at 256^3).  H and S go
+// through pat.mirror: their half layout under PatDiaSym, the full one otherwise.
 template <int U16, int U64, class Pat>
 static void launch_products(System& s, const Pat& pat, int which, double alpha, const void* x, void* y) {
   const int ntiles = s.npad / kSpmvBlock;
@@ -147,30 +150,41 @@ static void launch_products(System& s, const Pat& pat, int which, double alpha, 
       hipLaunchKernelGGL((spmv_a64_kernel<U64, Pat>), g64, block, 0, s.stream, pat, s.a_off, s.a_diag,
                          (const double*)x, (double*)y, s.n, ntiles);
       break;
-    case 1:
-      hipLaunchKernelGGL((spmv_h_kernel<U16, Pat, __half, __half, float>), g16, block, 0, s.stream, pat, s.h_off16,
+    case 1: {
+      const auto hv = pat.template mirror<false>((const __half*)s.h_off16, (const __half*)s.h_half[0]);
+      hipLaunchKernelGGL((spmv_h_kernel<U16, Pat, decltype(hv), __half, float>), g16, block, 0, s.stream, pat, hv,
                          s.h_diag16, (const __half*)x, (__half*)y, (float)alpha, s.n, ntiles);
       break;
-    case 2:
-      hipLaunchKernelGGL((spmv_s16_kernel<U16, Pat>), g16, block, 0, s.stream, pat, s.s_off16, (const __half*)x,
-                         (__half*)y, (float)(1.0 / alpha), s.n, ntiles);
+    }
+    case 2: {
+      const auto sv = pat.template mirror<true>((const __half*)s.s_off16, (const __half*)s.s_half[0]);
+      hipLaunchKernelGGL((spmv_s16_kernel<U16, Pat, decltype(sv)>), g16, block, 0, s.stream, pat, sv,
+                         (const __half*)x, (__half*)y, (float)(1.0 / alpha), s.n, ntiles);
       break;
-    case 3:
-      hipLaunchKernelGGL((spmv_h_kernel<U64, Pat, double, double, double>), g64, block, 0, s.stream, pat, s.h_off64,
+    }
+    case 3: {
+      const auto hv = pat.template mirror<false>((const double*)s.h_off64, (const double*)s.h_half[2]);
+      hipLaunchKernelGGL((spmv_h_kernel<U64, Pat, decltype(hv), double, double>), g64, block, 0, s.stream, pat, hv,
                          s.h_diag64, (const double*)x, (double*)y, alpha, s.n, ntiles);
       break;
-    case 4:
-      hipLaunchKernelGGL((spmv_h_kernel<U16, Pat, e4m3, __half, float>), g16, block, 0, s.stream, pat,
-                         (const e4m3*)s.h_off8, s.h_diag16, (const __half*)x, (__half*)y, (float)alpha, s.n, ntiles);
+    }
+    case 4: {
+      const auto hv = pat.template mirror<false>((const e4m3*)s.h_off8, (const e4m3*)s.h_half[3]);
+      hipLaunchKernelGGL((spmv_h_kernel<U16, Pat, decltype(hv), __half, float>), g16, block, 0, s.stream, pat, hv,
+                         s.h_diag16, (const __half*)x, (__half*)y, (float)alpha, s.n, ntiles);
       break;
+    }
   }
 }
 
+// Symmetric uniform offsets: H and S from their half layout (PatDiaSym), A
+// from the full one.
 template <int W>
-static PatDia<W> uniform_pattern(const System& s) {
-  PatDia<W> p;
+static PatDiaSym<W> uniform_pattern(const System& s) {
+  PatDiaSym<W> p;
   for (int j = 0; j < W; ++j) p.off[j] = s.dia_u[j];
   p.nmax = s.n - 1;
+  p.pad = s.half_pad;
   return p;
 }
 
@@ -183,9 +197,18 @@ extern "C" gadi_status gadi_spmv(gadi_handle* h, int32_t which, double alpha, co
     const gadi_status st = ensure_fp8_public(s);
     if (st != GADI_OK) return st;
   }
-  switch (s.dia_uniform) {
-    case 4: launch_products<2, 2>(s, uniform_pattern<4>(s), which, alpha, x, y); break;
-    case 6: launch_products<2, 2>(s, uniform_pattern<6>(s), which, alpha, x, y); break;
+  // the half layout of H and S for this product's value type (built on first use)
+  if (which != 0 && s.dia_sym) {
+    const int kind = which == 3 ? 2 : (which == 4 ? 3 : 0);
+    const void* hf = which == 3 ? (const void*)s.h_off64 : (which == 4 ? (const void*)s.h_off8 : (const void*)s.h_off16);
+    const void* sf = which == 3 ? (const void*)s.s_off64 : (which == 4 ? (const void*)s.s_off8 : (const void*)s.s_off16);
+    const gadi_status st = ensure_half(s, kind, hf, sf);
+    if (st != GADI_OK) return st;
+  }
+  const bool half = s.dia_sym && (which == 0 || s.h_half[which == 3 ? 2 : (which == 4 ? 3 : 0)]);
+  switch (half ? s.dia_uniform : 0) {
+    case 4: launch_products<4, 2>(s, uniform_pattern<4>(s), which, alpha, x, y); break;
+    case 6: launch_products<4, 2>(s, uniform_pattern<6>(s), which, alpha, x, y); break;
     default:
       launch_products<1, 1>(s, PatGeneric{Pattern{s.slice_ptr, s.col, s.slice_dia, s.dia_off, s.n - 1}}, which, alpha,
                          x, y);
