@@ -518,8 +518,8 @@ static __device__ __forceinline__ Red4 xcc_direct_allreduce(Grid& g, double (*sh
 }
 
 template <int BLOCK>
-static __device__ __forceinline__ Red4 grid_allreduce(Grid& g, double s0, double s1, double s2, double m3,
-                                                      bool& ok) {
+static __device__ __forceinline__ Red4 grid_allreduce_all(Grid& g, double s0, double s1, double s2, double m3,
+                                                          bool& ok) {
   constexpr int NW = BLOCK / 64;
   __shared__ double sh[NW][4];
   __shared__ int sh_abort;
@@ -649,6 +649,56 @@ static __device__ __forceinline__ Red4 grid_allreduce(Grid& g, double s0, double
   if (tid == 0) g.wait_ticks += wall_clock64() - t_enter;
   __syncthreads();  // shared state is rewritten by the next call
   return out;
+}
+
+// The relay and the master XCC protocols out of line: the launch-start relay
+// barrier and the non-default GADI_BARRIER choices call one copy, so that only
+// the default protocol's code sits at every phase end (a kernel inlining all
+// three at its ~40 call sites is about 3 times larger than the instruction
+// cache).  The grid state goes by value and comes back with the result, so it
+// stays in registers.
+struct GridRet {
+  Red4 out;
+  unsigned long long epoch;
+  long long wait_ticks;
+  bool ok;
+};
+template <int BLOCK>
+static __device__ __noinline__ GridRet grid_allreduce_ool(Grid g, double s0, double s1, double s2, double m3) {
+  GridRet r;
+  r.out = grid_allreduce_all<BLOCK>(g, s0, s1, s2, m3, r.ok);
+  r.epoch = g.epoch;
+  r.wait_ticks = g.wait_ticks;
+  return r;
+}
+
+// Device-wide all-reduce of the solve kernel: the master-free XCC protocol
+// inline, the others through grid_allreduce_ool.
+template <int BLOCK>
+static __device__ __forceinline__ Red4 grid_allreduce(Grid& g, double s0, double s1, double s2, double m3,
+                                                      bool& ok) {
+  if (g.kind == 2) {
+    constexpr int NW = BLOCK / 64;
+    __shared__ double sh[NW][4];
+    __shared__ int sh_abort;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const long long t_enter = tid == 0 ? wall_clock64() : 0;
+    const double a0 = wave_sum(s0), a1 = wave_sum(s1), a2 = wave_sum(s2), a3 = wave_max(m3);
+    if (lane == 0) {
+      sh[wid][0] = a0;
+      sh[wid][1] = a1;
+      sh[wid][2] = a2;
+      sh[wid][3] = a3;
+    }
+    wait_vmem();  // this wave's phase stores are in the L2 before the block arrives
+    __syncthreads();
+    return xcc_direct_allreduce<BLOCK>(g, sh, sh_abort, t_enter, ok);
+  }
+  const GridRet r = grid_allreduce_ool<BLOCK>(g, s0, s1, s2, m3);
+  g.epoch = r.epoch;
+  g.wait_ticks = r.wait_ticks;
+  ok = r.ok;
+  return r.out;
 }
 
 // Logical block index: blocks are dealt to the 8 XCDs round-robin, so blocks
