@@ -430,6 +430,9 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
   const AV* __restrict__ adiag = (const AV*)a.a_diag;
   const double* __restrict__ b = a.b;
 
+  // the lean loops of the Hestenes-Stiefel CG and of Craig's CGNE hold few
+  // loads per row: 512-thread blocks keep twice the tiles in flight there
+  constexpr int UL = (BLOCK == 512 && U > 1) ? 2 * U : U;
   const AT alpha = (AT)a.alpha;
   const AT inv_alpha = (AT)(1.0 / a.alpha);
   const AT two_m_omega = (AT)(2.0 - a.omega);
@@ -834,7 +837,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
               ST z;
               VT r;
             };
-            for_rows<BLOCK, U>(
+            for_rows<BLOCK, UL>(
                 t0, t1,
                 [&](unsigned row) {
                   struct {
@@ -872,7 +875,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
               VT p, q;
             };
             auto gv = [&](unsigned c) { return at(vr, c); };
-            for_rows<BLOCK, U>(
+            for_rows<BLOCK, UL>(
                 t0, t1,
                 [&](unsigned row) {
                   struct {
@@ -971,7 +974,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
               s0 += dr * dr;
             };
             if (its == 0) {
-              for_rows<BLOCK, U>(
+              for_rows<BLOCK, UL>(
                   t0, t1,
                   [&](unsigned row) {
                     struct {
@@ -987,7 +990,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
                   },
                   store);
             } else {
-              for_rows<BLOCK, U>(
+              for_rows<BLOCK, UL>(
                   t0, t1,
                   [&](unsigned row) {
                     struct {
@@ -1012,7 +1015,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
             gam = gnew;
             // p_{k+1} = (I - S/alpha) r_{k+1} + beta_k p_k
             double s1 = 0.0;
-            for_rows<BLOCK, U>(
+            for_rows<BLOCK, UL>(
                 t0, t1,
                 [&](unsigned row) {
                   struct {
