@@ -137,7 +137,14 @@ gadi_status gadi_set_stream(gadi_handle* h, void* stream);
  * (host or device per opts->on_device).  alpha > 0 and 0 <= omega < 2 (the
  * convergence domain of Theorem 1), tol >= 0.  On return x holds the last
  * iterate and info (may be NULL) is filled; the return value equals
- * info->status.  EINVAL for bad parameters. */
+ * info->status.  EINVAL for bad parameters.
+ * The whole solve is one persistent cooperative kernel launch on the handle's
+ * stream.  The first solve per handle and precision also times the candidate
+ * launch shapes and inner-solver forms (see gadi_solver_form) and builds the
+ * half layout of H and S it reads; both allocate, so that first call must not
+ * be captured in a graph.  GADI_BARRIER=relay|xcc|direct selects the device-wide
+ * barrier (default direct: XCC-hierarchical without a master block); all three
+ * give bit-identical results. */
 gadi_status gadi_ir_solve(gadi_handle* h, const double* b, double* x, double alpha, double omega,
                           double tol, const gadi_options* opts, gadi_solve_info* info);
 
