@@ -430,8 +430,9 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
   const AV* __restrict__ adiag = (const AV*)a.a_diag;
   const double* __restrict__ b = a.b;
 
-  // the lean loops of the Hestenes-Stiefel CG and of Craig's CGNE hold few
-  // loads per row: 512-thread blocks keep twice the tiles in flight there
+  // the lean loops of the Hestenes-Stiefel CG and of Craig's CGNE (and their
+  // start phases) hold few loads per row: 512-thread blocks keep twice the
+  // tiles in flight there
   constexpr int UL = (BLOCK == 512 && U > 1) ? 2 * U : U;
   const AT alpha = (AT)a.alpha;
   const AT inv_alpha = (AT)(1.0 / a.alpha);
@@ -454,7 +455,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
   int sweep = 0;
   long long ih = 0, is = 0;
 
-  // Operands of the recomputed r_{k+1} at a neighbouring row (fused form).
+  // Operands of the recomputed r_{k+1} at a neighbouring row (form 1).
   struct Rk3 {
     VT sp, w, r;
   };
@@ -794,7 +795,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
           VT p, q;
         };
         double s0 = 0.0, s1 = 0.0;
-        for_rows<BLOCK, U>(
+        for_rows<BLOCK, UL>(
             t0, t1,
             [&](unsigned row) {
               struct {
@@ -928,7 +929,7 @@ __device__ __forceinline__ bool solve_body(const SolveArgs& a, Red& red, const P
             AT g, p;
           };
           double s0 = 0.0, s1 = 0.0;
-          for_rows<BLOCK, U>(
+          for_rows<BLOCK, UL>(
               t0, t1,
               [&](unsigned row) {
                 struct {
