@@ -38,6 +38,7 @@ def test_status_strings_and_defaults():
     import paper_2501_04229_amd as gadi
     assert gadi.status_str(0) == "ok"
     assert gadi.status_str(4) == "diverged"
+    assert gadi.status_str(gadi.EPRUNED).startswith("pruned")
     assert gadi.status_str(99) == "unknown status"
     o = gadi.options("fp64")
     assert o.prec == 0 and o.eps_inner == 1e-6
