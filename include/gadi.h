@@ -208,6 +208,10 @@ gadi_status gadi_ir_solve_batched(gadi_handle* const* hs, int32_t nsys, const do
  *   which = 4: y = (alpha I + H) x   fp16 in/out, E4M3 off-diagonal values of H
  *              (the FP8 mode's operator; the first FP8 call on a handle encodes
  *              them, which allocates and synchronises: not under graph capture)
+ * On a uniform stencil layout H and S are read from their half layout (the
+ * positive offsets only; the products are the same bit for bit), which the
+ * first such call per value type builds if no solve has: that call allocates,
+ * so it must not be captured in a graph either.
  * Enqueued on the bound stream; does not synchronise. */
 gadi_status gadi_spmv(gadi_handle* h, int32_t which, double alpha, const void* x, void* y);
 
