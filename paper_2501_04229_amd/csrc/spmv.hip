@@ -17,17 +17,20 @@ gadi_status ensure_half(System& s, int kind, const void* hfull, const void* sful
 // as in the solver, measured slower here at 256^3).  x has the caller's
 // length n: rows past n read x at row n - 1 (an unconditional load, so no
 // branch drains the loads in flight) and write no y.
-constexpr int kSpmvBlock = 256;
+// threads per block: 512 for the half-precision products, 256 for the double
+// product of A (each measured best at 256^3)
+constexpr int kSpmvBlock16 = 512;
+constexpr int kSpmvBlock64 = 256;
 
 // y = A x in double (the residual's operator, step 1 of Algorithm 1)
 template <int U, class Pat>
-__global__ void __launch_bounds__(kSpmvBlock) spmv_a64_kernel(Pat pat, const double* __restrict__ off,
+__global__ void __launch_bounds__(kSpmvBlock64) spmv_a64_kernel(Pat pat, const double* __restrict__ off,
                                                              const double* __restrict__ diag,
                                                              const double* __restrict__ x, double* __restrict__ y,
                                                              int n, int ntiles) {
   const int t0 = blockIdx.x * U, t1 = t0 + U < ntiles ? t0 + U : ntiles;
   auto gx = [&](unsigned c) { return at(x, c); };
-  for_rows<kSpmvBlock, U>(
+  for_rows<kSpmvBlock64, U>(
       t0, t1,
       [&](unsigned row) {
         struct {
@@ -45,12 +48,12 @@ __global__ void __launch_bounds__(kSpmvBlock) spmv_a64_kernel(Pat pat, const dou
 // y = (alpha I + H) x: off-diagonal values (OV: a pointer to MT, or H's half
 // layout under PatDiaSym), diagonal and vectors VT, arithmetic in AT
 template <int U, class Pat, class OV, class VT, class AT>
-__global__ void __launch_bounds__(kSpmvBlock) spmv_h_kernel(Pat pat, OV off,
+__global__ void __launch_bounds__(kSpmvBlock16) spmv_h_kernel(Pat pat, OV off,
                                                            const VT* __restrict__ diag, const VT* __restrict__ x,
                                                            VT* __restrict__ y, AT alpha, int n, int ntiles) {
   const int t0 = blockIdx.x * U, t1 = t0 + U < ntiles ? t0 + U : ntiles;
   auto gx = [&](unsigned c) { return at(x, c); };
-  for_rows<kSpmvBlock, U>(
+  for_rows<kSpmvBlock16, U>(
       t0, t1,
       [&](unsigned row) {
         struct {
@@ -69,12 +72,12 @@ __global__ void __launch_bounds__(kSpmvBlock) spmv_h_kernel(Pat pat, OV off,
 
 // y = (I + S / alpha) x, half in/out, float arithmetic (OV as above)
 template <int U, class Pat, class OV>
-__global__ void __launch_bounds__(kSpmvBlock) spmv_s16_kernel(Pat pat, OV off,
+__global__ void __launch_bounds__(kSpmvBlock16) spmv_s16_kernel(Pat pat, OV off,
                                                              const __half* __restrict__ x, __half* __restrict__ y,
                                                              float inv_alpha, int n, int ntiles) {
   const int t0 = blockIdx.x * U, t1 = t0 + U < ntiles ? t0 + U : ntiles;
   auto gx = [&](unsigned c) { return at(x, c); };
-  for_rows<kSpmvBlock, U>(
+  for_rows<kSpmvBlock16, U>(
       t0, t1,
       [&](unsigned row) {
         struct {
@@ -143,35 +146,36 @@ using namespace gadi;
 // through pat.mirror: their half layout under PatDiaSym, the full one otherwise.
 template <int U16, int U64, class Pat>
 static void launch_products(System& s, const Pat& pat, int which, double alpha, const void* x, void* y) {
-  const int ntiles = s.npad / kSpmvBlock;
-  const dim3 g16((ntiles + U16 - 1) / U16), g64((ntiles + U64 - 1) / U64), block(kSpmvBlock);
+  const int nt16 = s.npad / kSpmvBlock16, nt64 = s.npad / kSpmvBlock64;
+  const dim3 g16((nt16 + U16 - 1) / U16), g64((nt64 + U64 - 1) / U64), b16(kSpmvBlock16), b64(kSpmvBlock64);
   switch (which) {
     case 0:
-      hipLaunchKernelGGL((spmv_a64_kernel<U64, Pat>), g64, block, 0, s.stream, pat, s.a_off, s.a_diag,
-                         (const double*)x, (double*)y, s.n, ntiles);
+      hipLaunchKernelGGL((spmv_a64_kernel<U64, Pat>), g64, b64, 0, s.stream, pat, s.a_off, s.a_diag,
+                         (const double*)x, (double*)y, s.n, nt64);
       break;
     case 1: {
       const auto hv = pat.template mirror<false>((const __half*)s.h_off16, (const __half*)s.h_half[0]);
-      hipLaunchKernelGGL((spmv_h_kernel<U16, Pat, decltype(hv), __half, float>), g16, block, 0, s.stream, pat, hv,
-                         s.h_diag16, (const __half*)x, (__half*)y, (float)alpha, s.n, ntiles);
+      hipLaunchKernelGGL((spmv_h_kernel<U16, Pat, decltype(hv), __half, float>), g16, b16, 0, s.stream, pat, hv,
+                         s.h_diag16, (const __half*)x, (__half*)y, (float)alpha, s.n, nt16);
       break;
     }
     case 2: {
       const auto sv = pat.template mirror<true>((const __half*)s.s_off16, (const __half*)s.s_half[0]);
-      hipLaunchKernelGGL((spmv_s16_kernel<U16, Pat, decltype(sv)>), g16, block, 0, s.stream, pat, sv,
-                         (const __half*)x, (__half*)y, (float)(1.0 / alpha), s.n, ntiles);
+      hipLaunchKernelGGL((spmv_s16_kernel<U16, Pat, decltype(sv)>), g16, b16, 0, s.stream, pat, sv,
+                         (const __half*)x, (__half*)y, (float)(1.0 / alpha), s.n, nt16);
       break;
     }
     case 3: {
       const auto hv = pat.template mirror<false>((const double*)s.h_off64, (const double*)s.h_half[2]);
-      hipLaunchKernelGGL((spmv_h_kernel<U64, Pat, decltype(hv), double, double>), g64, block, 0, s.stream, pat, hv,
-                         s.h_diag64, (const double*)x, (double*)y, alpha, s.n, ntiles);
+      // the double H product runs the 512-thread kernel with the double tiling
+      hipLaunchKernelGGL((spmv_h_kernel<U64, Pat, decltype(hv), double, double>), dim3((nt16 + U64 - 1) / U64), b16, 0,
+                         s.stream, pat, hv, s.h_diag64, (const double*)x, (double*)y, alpha, s.n, nt16);
       break;
     }
     case 4: {
       const auto hv = pat.template mirror<false>((const e4m3*)s.h_off8, (const e4m3*)s.h_half[3]);
-      hipLaunchKernelGGL((spmv_h_kernel<U16, Pat, decltype(hv), __half, float>), g16, block, 0, s.stream, pat, hv,
-                         s.h_diag16, (const __half*)x, (__half*)y, (float)alpha, s.n, ntiles);
+      hipLaunchKernelGGL((spmv_h_kernel<U16, Pat, decltype(hv), __half, float>), g16, b16, 0, s.stream, pat, hv,
+                         s.h_diag16, (const __half*)x, (__half*)y, (float)alpha, s.n, nt16);
       break;
     }
   }
