@@ -259,13 +259,24 @@ __global__ void __launch_bounds__(kSylBlock) syl_col_local_kernel(const IT* __re
   }
 }
 
-// One thread per column: the chunk-boundary chains.  B_c = y_{s_c - 1}
-// (B_0 = 0), E_c = z_{e_c} (E_last = 0).  The chain inputs are loaded kBatch
-// chunks at a time, so the loads of a batch are in flight together.  With zmx
-// given (column direction), the kernel also bounds max |G| = |gscale| max |z|
-// by max over chunks of max|z^| + |B_c| max|q| + |E_c| max|h| into gmax.
-constexpr int kBatch = 32;
-constexpr int kChainBlock = 64;
+// The chunk-boundary chains: B_c = y_{s_c - 1} (B_0 = 0), E_c = z_{e_c}
+// (E_last = 0).  Across chunks each chain is an affine recurrence,
+//   B_{c+1} = yend_c + f_{e_c - 1} B_c,
+//   E_{c-1} = zbeg_c + B_c q_{s_c} + h_{s_c} E_c,
+// so it runs as a two-level scan: a block holds kChainCols columns and splits
+// each column's chunks into kChainParts consecutive ranges, one per thread.
+// A thread composes the affine maps of its range, one thread per column chains
+// the composed maps through LDS, and every thread then reruns its range from
+// its true entry value, writing the boundary values.  A range of at most
+// kChainBatch chunks keeps its inputs in registers through both chains (one
+// round of loads); a longer one reloads them per pass, and its backward chain
+// reads back the B_c its own thread wrote.  With zmx given (column direction), the kernel
+// also bounds max |G| = |gscale| max |z| by max over chunks of
+// max|z^| + |B_c| max|q| + |E_c| max|h| into gmax.
+constexpr int kChainCols = 16;
+constexpr int kChainParts = 16;
+constexpr int kChainBlock = kChainCols * kChainParts;
+constexpr int kChainBatch = 4;  // chunks whose loads are issued together
 
 template <class IT>
 __global__ void __launch_bounds__(kChainBlock) syl_chain_kernel(const IT* __restrict__ yend, const IT* __restrict__ zbeg,
@@ -275,59 +286,187 @@ __global__ void __launch_bounds__(kChainBlock) syl_chain_kernel(const IT* __rest
                                                               unsigned* __restrict__ gmax,
                                                               const SylCtl* __restrict__ ctl) {
   if (ctl->done) return;
-  const int j = blockIdx.x * kChainBlock + threadIdx.x;
-  IT bound = 0;
-  if (j < width) {
-  IT b = 0;
-  for (int c0 = 0; c0 < nchunks; c0 += kBatch) {
-    IT ye[kBatch], ff[kBatch];
+  __shared__ IT s_c[kChainParts][kChainCols], s_m[kChainParts][kChainCols];
+  __shared__ float s_bound[kChainBlock / 64];
+  const int col = threadIdx.x % kChainCols, part = threadIdx.x / kChainCols;
+  const int j = blockIdx.x * kChainCols + col;
+  const bool live = j < width;
+  const int jc = live ? j : width - 1;
+  const int per = (nchunks + kChainParts - 1) / kChainParts;
+  const int lo = part * per < nchunks ? part * per : nchunks;
+  const int hi = lo + per < nchunks ? lo + per : nchunks;
+  // entry values of the parts, from the composed maps (cst, mul) of every part:
+  // forward = true chains part 0 upward, else part kChainParts - 1 downward
+  auto chain_parts = [&](IT cst, IT mul, bool forward) -> IT {
+    s_c[part][col] = cst;
+    s_m[part][col] = mul;
+    __syncthreads();
+    if (part == 0) {
+      IT v = 0;
+      for (int k = 0; k < kChainParts; ++k) {
+        const int p = forward ? k : kChainParts - 1 - k;
+        const IT c = s_c[p][col], m = s_m[p][col];
+        s_c[p][col] = v;
+        v = c + m * v;
+      }
+    }
+    __syncthreads();
+    const IT entry = s_c[part][col];
+    __syncthreads();  // the arrays are reused by the next chain
+    return entry;
+  };
+  // block maximum of the column bound into gmax
+  auto chain_bound = [&](IT bound) {
+    if (!zmx) return;
+    float v = live ? (float)(fabs(gscale) * bound) : 0.f;
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) s_bound[threadIdx.x / 64] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float mx = s_bound[0];
+      for (int w = 1; w < kChainBlock / 64; ++w) mx = fmaxf(mx, s_bound[w]);
+      atomicMax(gmax, __float_as_uint(mx));
+    }
+  };
+  if (per <= kChainBatch) {
+    // a range of at most kChainBatch chunks: every input of the range is
+    // loaded at once and kept in registers through both chains
+    IT ye[kChainBatch], ff[kChainBatch], zb[kChainBatch], qq[kChainBatch], hh[kChainBatch], zm[kChainBatch],
+        bb[kChainBatch];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int c = c0 + u < nchunks ? c0 + u : nchunks - 1;
+    for (int u = 0; u < kChainBatch; ++u) {
+      // an empty range has lo = hi = nchunks: its clamped loads stay in bounds
+      const int c = lo + u < hi ? lo + u : hi - 1;
+      const int s = c * kChunk;
       const int e = (c + 1) * kChunk < F.len ? (c + 1) * kChunk : F.len;
-      ye[u] = yend[(size_t)c * width + j];
+      ye[u] = yend[(size_t)c * width + jc];
+      ff[u] = F.f[e - 1];
+      zb[u] = zbeg[(size_t)c * width + jc];
+      qq[u] = F.q[s];
+      hh[u] = F.h[s];
+      zm[u] = zmx ? zmx[(size_t)c * width + jc] : IT(0);
+    }
+    IT cst = 0, mul = 1;
+#pragma unroll
+    for (int u = 0; u < kChainBatch; ++u)
+      if (lo + u < hi) {
+        cst = ye[u] + ff[u] * cst;
+        mul = ff[u] * mul;
+      }
+    IT b = chain_parts(cst, mul, true);
+#pragma unroll
+    for (int u = 0; u < kChainBatch; ++u) {
+      bb[u] = b;
+      if (lo + u < hi) {
+        if (live) Bc[(size_t)(lo + u) * width + j] = b;
+        b = ye[u] + ff[u] * b;
+      }
+    }
+    cst = 0;
+    mul = 1;
+#pragma unroll
+    for (int u = kChainBatch - 1; u >= 0; --u)
+      if (lo + u < hi) {
+        cst = zb[u] + bb[u] * qq[u] + hh[u] * cst;
+        mul = hh[u] * mul;
+      }
+    IT ez = chain_parts(cst, mul, false);
+    IT bound = 0;
+#pragma unroll
+    for (int u = kChainBatch - 1; u >= 0; --u) {
+      const int c = lo + u;
+      if (c < hi) {
+        if (live) Ec[(size_t)c * width + j] = ez;
+        if (zmx) bound = fmax(bound, zm[u] + fabs(bb[u]) * F.qm[c] + fabs(ez) * F.hm[c]);
+        ez = zb[u] + bb[u] * qq[u] + ez * hh[u];
+      }
+    }
+    chain_bound(bound);
+    return;
+  }
+  // forward chain: compose, chain the parts, rerun writing B_c
+  IT cst = 0, mul = 1;
+  for (int c0 = lo; c0 < hi; c0 += kChainBatch) {
+    IT ye[kChainBatch], ff[kChainBatch];
+#pragma unroll
+    for (int u = 0; u < kChainBatch; ++u) {
+      const int c = c0 + u < hi ? c0 + u : hi - 1;
+      const int e = (c + 1) * kChunk < F.len ? (c + 1) * kChunk : F.len;
+      ye[u] = yend[(size_t)c * width + jc];
       ff[u] = F.f[e - 1];
     }
-    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
+    for (int u = 0; u < kChainBatch; ++u)
+      if (c0 + u < hi) {
+        cst = ye[u] + ff[u] * cst;
+        mul = ff[u] * mul;
+      }
+  }
+  IT b = chain_parts(cst, mul, true);
+  for (int c0 = lo; c0 < hi; c0 += kChainBatch) {
+    IT ye[kChainBatch], ff[kChainBatch];
+#pragma unroll
+    for (int u = 0; u < kChainBatch; ++u) {
+      const int c = c0 + u < hi ? c0 + u : hi - 1;
+      const int e = (c + 1) * kChunk < F.len ? (c + 1) * kChunk : F.len;
+      ye[u] = yend[(size_t)c * width + jc];
+      ff[u] = F.f[e - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kChainBatch; ++u) {
       const int c = c0 + u;
-      if (c < nchunks) {
-        Bc[(size_t)c * width + j] = b;
+      if (c < hi) {
+        if (live) Bc[(size_t)c * width + j] = b;
         b = ye[u] + ff[u] * b;
       }
     }
   }
-  IT ez = 0;
-  for (int c1 = nchunks - 1; c1 >= 0; c1 -= kBatch) {
-    IT zb[kBatch], bb[kBatch], qq[kBatch], hh[kBatch], zm[kBatch];
+  // backward chain over the same ranges, chunks in descending order; a live
+  // thread reads back the B_c it wrote above
+  cst = 0;
+  mul = 1;
+  for (int c1 = hi - 1; c1 >= lo; c1 -= kChainBatch) {
+    IT kk[kChainBatch], hh[kChainBatch];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int c = c1 - u >= 0 ? c1 - u : 0;
+    for (int u = 0; u < kChainBatch; ++u) {
+      const int c = c1 - u >= lo ? c1 - u : lo;
       const int s = c * kChunk;
-      zb[u] = zbeg[(size_t)c * width + j];
-      bb[u] = Bc[(size_t)c * width + j];
+      const IT bb = live ? Bc[(size_t)c * width + j] : IT(0);
+      kk[u] = zbeg[(size_t)c * width + jc] + bb * F.q[s];
+      hh[u] = F.h[s];
+    }
+#pragma unroll
+    for (int u = 0; u < kChainBatch; ++u)
+      if (c1 - u >= lo) {
+        cst = kk[u] + hh[u] * cst;
+        mul = hh[u] * mul;
+      }
+  }
+  IT ez = chain_parts(cst, mul, false);
+  IT bound = 0;
+  for (int c1 = hi - 1; c1 >= lo; c1 -= kChainBatch) {
+    IT zb[kChainBatch], bb[kChainBatch], qq[kChainBatch], hh[kChainBatch], zm[kChainBatch];
+#pragma unroll
+    for (int u = 0; u < kChainBatch; ++u) {
+      const int c = c1 - u >= lo ? c1 - u : lo;
+      const int s = c * kChunk;
+      zb[u] = zbeg[(size_t)c * width + jc];
+      bb[u] = live ? Bc[(size_t)c * width + j] : IT(0);
       qq[u] = F.q[s];
       hh[u] = F.h[s];
-      zm[u] = zmx ? zmx[(size_t)c * width + j] : IT(0);
+      zm[u] = zmx ? zmx[(size_t)c * width + jc] : IT(0);
     }
-    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
+    for (int u = 0; u < kChainBatch; ++u) {
       const int c = c1 - u;
-      if (c >= 0) {
-        Ec[(size_t)c * width + j] = ez;
+      if (c >= lo) {
+        if (live) Ec[(size_t)c * width + j] = ez;
         if (zmx) bound = fmax(bound, zm[u] + fabs(bb[u]) * F.qm[c] + fabs(ez) * F.hm[c]);
         ez = zb[u] + bb[u] * qq[u] + ez * hh[u];
       }
     }
   }
-  }
-  if (zmx) {
-    float v = (float)(fabs(gscale) * bound);
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(gmax, __float_as_uint(v));
-  }
+  chain_bound(bound);
 }
 
 // Power-of-two scale that brings max |g| into [1/2, 1) (1 if g is zero).
@@ -600,13 +739,13 @@ static void enqueue_sweep(SylSystem& S, double alpha, double omega) {
                      S.hist_cap, MODE == 2 ? 0 : 1, S.gmax);
   hipLaunchKernelGGL((syl_col_local_kernel<IT, MODE>), dim3((n + kSylBlock - 1) / kSylBlock, pc), dim3(kSylBlock), 0,
                      S.stream, R, Fc, S.ctl, n, Zh, yend, zbeg, zmx);
-  hipLaunchKernelGGL((syl_chain_kernel<IT>), dim3((n + kChainBlock - 1) / kChainBlock), dim3(kChainBlock), 0, S.stream,
+  hipLaunchKernelGGL((syl_chain_kernel<IT>), dim3((n + kChainCols - 1) / kChainCols), dim3(kChainBlock), 0, S.stream,
                      yend, zbeg, Fc, pc, n, Bc, Ec, zmx, gs, S.gmax, S.ctl);
   // the row solves read z^ (Zh) and the column chains (Bc, Ec), and write their
   // chunk-local solutions to R and their chain inputs to yend, zbeg
   hipLaunchKernelGGL((syl_row_local_kernel<IT, MODE>), dim3(pr, (m + 63) / 64), dim3(64), 0, S.stream, Zh, Bc, Ec, Fc,
                      gs, Fr, S.gmax, m, n, R, yend, zbeg, S.ctl);
-  hipLaunchKernelGGL((syl_chain_kernel<IT>), dim3((m + kChainBlock - 1) / kChainBlock), dim3(kChainBlock), 0, S.stream,
+  hipLaunchKernelGGL((syl_chain_kernel<IT>), dim3((m + kChainCols - 1) / kChainCols), dim3(kChainBlock), 0, S.stream,
                      yend, zbeg, Fr, pr, m, Bc, Ec, (const IT*)nullptr, IT(0), S.gmax, S.ctl);
   hipLaunchKernelGGL((syl_row_fix_update_kernel<IT, MODE>), g2, dim3(kSylBlock), 0, S.stream, R, Bc, Ec, Fr, S.gmax,
                      S.ctl, m, n, S.dX);

@@ -7,11 +7,13 @@
   solution (Bartels-Stewart or the manufactured one) obeys the forward bound
   ||X - X*||_F <= ||R||_F / lambda_min(sym(L)), lambda_min(sym(L)) =
   lambda_min((A + A^T)/2) + lambda_min((B + B^T)/2) for L = I (x) A + B^T (x) I;
-- shapes with ragged chunks (64-row chunks), single rows and columns, non-square;
+- shapes with ragged chunks (64-row chunks), single rows and columns, non-square,
+  and more chunks per column than the boundary chains' ranges;
 - argument checks and device pointers.
 """
 import numpy as np
 import pytest
+import scipy.linalg as sla
 
 import gadi_inputs as gi
 from oracle import sylvester as osyl
@@ -31,6 +33,11 @@ CASES = [
     ("rand1x5", lambda: (gi.random_tridiag(1, 5), gi.random_tridiag(5, 6))),
     ("rand5x1", lambda: (gi.random_tridiag(5, 7), gi.random_tridiag(1, 8))),
     ("paper257_r1", lambda: (gi.paper_tridiag(257, 1.0), gi.paper_tridiag(257, 1.0))),
+    # 21 and 18 chunks: more chunks than a chain kernel's 16 ranges per column, last range short
+    ("rand1300x1100", lambda: (gi.random_tridiag(1300, 9), gi.random_tridiag(1100, 10))),
+    # 71 chunks: more than 4 per range, the chains' reloading path, in each direction
+    ("rand4500x40", lambda: (gi.random_tridiag(4500, 12), gi.random_tridiag(40, 13))),
+    ("rand40x4500", lambda: (gi.random_tridiag(40, 14), gi.random_tridiag(4500, 15))),
 ]
 
 
@@ -42,8 +49,9 @@ def case(request):
 
 
 def lam_min_sym(T):
-    D = osyl.dense(T)
-    return float(np.linalg.eigvalsh((D + D.T) / 2.0)[0])
+    """Smallest eigenvalue of (T + T^T)/2, itself tridiagonal: diagonal d, off-diagonal (sub + sup)/2."""
+    sub, d, sup = (np.asarray(v, dtype=np.float64) for v in T)
+    return float(sla.eigvalsh_tridiagonal(d, (sub + sup) / 2.0, select="i", select_range=(0, 0))[0])
 
 
 def _relres(A, B, C, X):
@@ -85,7 +93,6 @@ def test_low_precision_inner_solves_reach_the_double_residual(case, prec):
 
 
 def test_fixed_point_is_the_bartels_stewart_solution():
-    import scipy.linalg as sla
     A, B = gi.random_tridiag(40, 21), gi.random_tridiag(33, 22)
     C = np.random.default_rng(23).normal(size=(40, 33))
     g = gadi.Sylvester(A, B)
