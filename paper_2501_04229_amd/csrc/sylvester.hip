@@ -225,7 +225,7 @@ __global__ void __launch_bounds__(kSylBlock) syl_col_local_kernel(const IT* __re
   if (ctl->done) return;
   const IT scale = (IT)ctl->scale1;
   const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * kSylBlock + threadIdx.x;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
   const int s = c * kChunk;
   const int len = F.len - s < kChunk ? F.len - s : kChunk;
@@ -737,8 +737,11 @@ static void enqueue_sweep(SylSystem& S, double alpha, double omega) {
                      S.dA + 2 * m, S.dB, S.dB + n, S.dB + 2 * n, R, m, n, S.part, S.ctl);
   hipLaunchKernelGGL(syl_reduce_kernel, dim3(1), dim3(kSylBlock), 0, S.stream, S.part, S.nparts, S.ctl, S.dhist,
                      S.hist_cap, MODE == 2 ? 0 : 1, S.gmax);
-  hipLaunchKernelGGL((syl_col_local_kernel<IT, MODE>), dim3((n + kSylBlock - 1) / kSylBlock, pc), dim3(kSylBlock), 0,
-                     S.stream, R, Fc, S.ctl, n, Zh, yend, zbeg, zmx);
+  // column chunks: one wavefront per block unless 256-thread blocks already
+  // give a few blocks per compute unit
+  const int cb = (size_t)((n + kSylBlock - 1) / kSylBlock) * pc >= 1024 ? kSylBlock : 64;
+  hipLaunchKernelGGL((syl_col_local_kernel<IT, MODE>), dim3((n + cb - 1) / cb, pc), dim3(cb), 0, S.stream, R, Fc,
+                     S.ctl, n, Zh, yend, zbeg, zmx);
   hipLaunchKernelGGL((syl_chain_kernel<IT>), dim3((n + kChainCols - 1) / kChainCols), dim3(kChainBlock), 0, S.stream,
                      yend, zbeg, Fc, pc, n, Bc, Ec, zmx, gs, S.gmax, S.ctl);
   // the row solves read z^ (Zh) and the column chains (Bc, Ec), and write their
