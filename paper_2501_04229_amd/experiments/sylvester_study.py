@@ -15,6 +15,8 @@ in [0.01, 10] for each r, half-precision inner solves.
 Part 3: device time per sweep at n = 1024 and 4096 (r = 0.1, alpha = 0.5) for
 the three inner precisions, with the sweep's algorithmic HBM bytes per element
 (double X and C, inner-type work arrays) and the rate they imply.
+--copy-calibration ends the run with one elementwise copy of known size, so that
+hardware byte counters taken over the run can be scaled to bytes.
 
 A = B = M + 2 r N + 100/(n+1)^2 I, M = Tridiag(-1, 2, -1), N = Tridiag(0.5, 0,
 -0.5); the right-hand side is C = A 1 + 1 B, so X* = 1 (all ones).  The section
@@ -142,6 +144,9 @@ def main():
     ap.add_argument("--time-sweeps", type=int, default=500)
     ap.add_argument("--parts", default="123")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with one elementwise copy of 2^26 floats (reads and writes 256 MiB) "
+                         "to calibrate hardware byte counters")
     a = ap.parse_args()
     import torch
     if not torch.cuda.is_available():
@@ -156,6 +161,11 @@ def main():
     if "3" in a.parts:
         res["timing"] = part3((1024, 4096), dev, a.time_sweeps)
     res["wall_seconds"] = time.time() - t0
+    if a.copy_calibration:
+        xc = torch.ones(1 << 26, device=dev, dtype=torch.float32)
+        yc = torch.empty_like(xc)
+        torch.mul(xc, 1.0, out=yc)
+        torch.cuda.synchronize()
     if a.out:
         with open(a.out, "w") as f:
             json.dump(res, f, indent=1)

@@ -4,6 +4,8 @@
            [--copy-bytes BYTES]
     python -m paper_2501_04229_amd.rocprof_summary --traffic FETCH.db WRITE.db --kernel SUBSTR
            --launches L --copy-bytes BYTES
+    python -m paper_2501_04229_amd.rocprof_summary --traffic FETCH.db WRITE.db --kernel SUBSTR --by-grid
+           --copy-bytes BYTES
 
 The second form combines a FETCH_SIZE run and a WRITE_SIZE run of the same
 command: the dispatches of the kernels matching SUBSTR, taken in order, end
@@ -139,6 +141,34 @@ def traffic(fetch_db, write_db, substr, launches, copy_bytes):
     return "\n".join(out)
 
 
+def traffic_by_grid(fetch_db, write_db, substr, copy_bytes):
+    """Mean HBM bytes per dispatch of each (kernel, launch grid, block) matching substr, from a FETCH_SIZE and a
+    WRITE_SIZE counter run, each scaled by its own copy calibration."""
+    import sqlite3
+    per = {}
+    scales = []
+    for db, counter in ((fetch_db, "FETCH_SIZE"), (write_db, "WRITE_SIZE")):
+        c = sqlite3.connect(db)
+        scale = copy_scale(c, counter, copy_bytes)
+        scales.append(f"{counter} {scale:.1f}")
+        rows = c.execute("select dispatch_id, kernel_name, grid_size, workgroup_size, value from counters_collection "
+                         "where counter_name = ? and kernel_name like ?", (counter, f"%{substr}%")).fetchall()
+        by = {}
+        for did, name, grid, wg, v in rows:
+            key = (name.split("(")[0].replace("void ", ""), grid, wg)
+            by.setdefault(key, {}).setdefault(did, 0.0)
+            by[key][did] += v
+        for key, d in by.items():
+            per.setdefault(key, {})[counter] = (len(d), sum(d.values()) / len(d) * scale)
+    out = ["copy calibration (bytes per counter unit): " + ", ".join(scales), "",
+           "| kernel | grid threads | block | dispatches | fetch MB | write MB | total MB |", "|---|---|---|---|---|---|---|"]
+    for (name, grid, wg), v in sorted(per.items(), key=lambda kv: (kv[0][1], kv[0][0])):
+        nd, f = v.get("FETCH_SIZE", (0, float("nan")))
+        _, w = v.get("WRITE_SIZE", (0, float("nan")))
+        out.append(f"| `{name}` | {grid} | {wg} | {nd} | {f / 1e6:.2f} | {w / 1e6:.2f} | {(f + w) / 1e6:.2f} |")
+    return "\n".join(out)
+
+
 def source_hash(root):
     """sha256 over the sources that fix the timed launches: libgadi's sources, the
     predictor (weights and solve_auto) and the workload generator."""
@@ -169,8 +199,12 @@ def main():
     ap.add_argument("--min-ms", type=float, default=0.0)
     ap.add_argument("--copy-bytes", type=float, default=0.0)
     ap.add_argument("--by-grid", action="store_true",
-                    help="kernel trace: group the matching launches by kernel and launch grid")
+                    help="group the matching launches by kernel and launch grid (kernel trace: durations; "
+                         "with --traffic: mean HBM bytes per dispatch)")
     a = ap.parse_args()
+    if a.traffic and a.by_grid:
+        print(traffic_by_grid(a.traffic[0], a.traffic[1], a.kernel, a.copy_bytes))
+        return
     if a.traffic:
         print(traffic(a.traffic[0], a.traffic[1], a.kernel, a.launches, a.copy_bytes))
         root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
