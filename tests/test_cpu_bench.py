@@ -1,5 +1,6 @@
 """Host logic of bench.py (no GPU): the algorithmic byte model behind
-roofline.achieved, the traffic summary's staleness rule, and the one-GPU rule."""
+roofline.achieved, the traffic summary's staleness rule, the copy-calibrated
+counter summaries that give roofline.traffic, and the one-GPU rule."""
 import os
 import subprocess
 import sys
@@ -98,3 +99,49 @@ def test_parity_tolerance_closed_form():
     xs, b = gi.rhs_for(A, "ones")
     t = bench.parity_tolerance(A, b, xs)
     assert t == min(1e-10, 0.9 * (1e-8 * lam * np.linalg.norm(xs) / np.linalg.norm(b) - 1e-13))
+
+
+def _counter_db(path, counter, rows):
+    """A counter database with the columns the summary reads: rows of
+    (dispatch_id, kernel_name, grid_size, workgroup_size, value); a dispatch may
+    have several rows (per-instance readings), which add up."""
+    import sqlite3
+    c = sqlite3.connect(str(path))
+    c.execute("create table counters_collection (dispatch_id int, kernel_name text, grid_size int, "
+              "workgroup_size int, counter_name text, value real)")
+    c.executemany("insert into counters_collection values (?, ?, ?, ?, ?, ?)",
+                  [(d, k, g, w, counter, v) for d, k, g, w, v in rows])
+    c.commit()
+    c.close()
+    return str(path)
+
+
+def test_counter_traffic_is_copy_calibrated(tmp_path):
+    """The copy dispatch fixes the bytes per counter unit of each run; the timed launches
+    are the `launches` dispatches before the last matching one, and per-(kernel, grid)
+    means keep the sizes of one kernel apart."""
+    import paper_2501_04229_amd.rocprof_summary as rs
+    copy = 1 << 20
+    # fetch counter: 1 unit = 2 bytes (the copy reads 2^20 bytes and reads 2^19); write: 1 unit = 4 bytes
+    f = _counter_db(tmp_path / "f.db", "FETCH_SIZE", [
+        (1, "gadi::solve_kernel<A>", 100, 10, 10e6), (1, "gadi::solve_kernel<A>", 100, 10, 5e6),
+        (2, "gadi::solve_kernel<A>", 100, 10, 30e6),
+        (3, "gadi::solve_kernel<A>", 200, 10, 70e6),
+        (4, "gadi::solve_kernel<A>", 200, 10, 1000e6),
+        (5, "elementwise_kernel<copy>", 1, 1, copy / 2)])
+    w = _counter_db(tmp_path / "w.db", "WRITE_SIZE", [
+        (1, "gadi::solve_kernel<A>", 100, 10, 1e6), (2, "gadi::solve_kernel<A>", 100, 10, 3e6),
+        (3, "gadi::solve_kernel<A>", 200, 10, 5e6), (4, "gadi::solve_kernel<A>", 200, 10, 500e6),
+        (5, "elementwise_kernel<copy>", 1, 1, copy / 4)])
+    out = rs.traffic(f, w, "solve_kernel", 2, copy)
+    # timed launches: dispatches 2 and 3 (the last matching one, 4, is the reference solve)
+    # fetch (30 + 70) * 2 = 200 MB, write (3 + 5) * 4 = 32 MB, over 2 launches
+    assert "traffic_bytes_per_launch: 1.160000e+08" in out
+    table = rs.traffic_by_grid(f, w, "solve_kernel", copy)
+    rows = {ln.split("|")[2].strip(): ln for ln in table.splitlines() if ln.startswith("| `")}
+    # grid 100 (MB columns): dispatch 1 sums its two readings (15e6 units) and dispatch 2 reads 30e6: mean 22.5e6
+    # units = 45 MB; writes (1 + 3) / 2 = 2e6 units = 8 MB
+    cells = [x.strip() for x in rows["100"].split("|")]
+    assert cells[4] == "2" and float(cells[5]) == 45.0 and float(cells[6]) == 8.0
+    cells = [x.strip() for x in rows["200"].split("|")]
+    assert float(cells[5]) == (70 + 1000) / 2 * 2 and float(cells[7]) == 1070.0 + (5 + 500) / 2 * 4
